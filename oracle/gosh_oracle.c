@@ -1,0 +1,377 @@
+/*
+ * GOSH CPU oracle (test infrastructure only) -- see gosh_oracle.h.
+ *
+ * Readings of the paper that this file fixes (each applied identically by
+ * the tests and the HIP path):
+ *  - UpdateEmbed (Algorithm 1): score = (b - sigma(M[v].M[s])) * lr; the
+ *    source row is updated first and the sample row then uses the updated
+ *    source row (literal statement order).
+ *  - sigma(x) = 1 / (1 + exp(-x)), no clamp or table.
+ *  - Positive sample: uniform over the neighbours of src; a source with no
+ *    neighbour skips its positive but still does its negatives.  Negatives
+ *    are uniform over V_i; a negative equal to src is skipped.  A sample that
+ *    repeats within one source sees that source's earlier update of it.
+ *  - hub^2 restriction with delta = |E_i|/|V_i| read as nnz/n (average CSR
+ *    degree), tested exactly as deg * n <= nnz.
+ *  - Ordering: counting sort by degree, larger degree first, ties in
+ *    ascending vertex id.  Cluster ids are handed out in processing order.
+ *  - Coarse graph: intra-cluster edges dropped, duplicates merged, rows
+ *    sorted, unweighted.
+ */
+#include "gosh_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 bit     */
+/* multiplies mixing the four counter words, with a Weyl-sequence key        */
+/* schedule.                                                                 */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_stream_block(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                      int64_t src, uint32_t kind, uint32_t slot, uint32_t block,
+                      uint32_t out[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = (uint32_t)src;
+    ctr[1] = (uint32_t)epoch;
+    ctr[2] = ((uint32_t)level & 0xFFu) | (tag << 8);
+    ctr[3] = (kind << 24) | ((slot & 0xFFu) << 16) | (block & 0xFFFFu);
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* floor(r * N / 2^32): maps a uniform 32-bit word onto [0, N). */
+static int64_t scale_word(uint32_t r, int64_t N)
+{
+    return (int64_t)(((uint64_t)r * (uint64_t)N) >> 32);
+}
+
+void orc_draw_samples(const int64_t* offsets, const int32_t* indices, int64_t n,
+                      uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                      int64_t src, int32_t k, int32_t* out)
+{
+    uint32_t w[64];
+    int32_t nwords = 1 + k;
+    for (int32_t b = 0; 4 * b < nwords; ++b)
+        orc_stream_block(seed, level, tag, epoch, src, 0u, 0u, (uint32_t)b, w + 4 * b);
+    int64_t deg = offsets[src + 1] - offsets[src];
+    out[0] = deg > 0 ? indices[offsets[src] + scale_word(w[0], deg)] : -1;
+    for (int32_t t = 1; t <= k; ++t)
+        out[t] = (int32_t)scale_word(w[t], n);
+}
+
+uint32_t orc_sr_bits(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                     int64_t src, uint32_t slot, int32_t e)
+{
+    uint32_t w[4];
+    orc_stream_block(seed, level, tag, epoch, src, 1u, slot, (uint32_t)(e / 8), w);
+    int32_t h = e % 8;
+    uint32_t word = w[h / 2];
+    return (h & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
+
+/* ------------------------------------------------------------------------ */
+/* BF16 storage                                                              */
+/* ------------------------------------------------------------------------ */
+static uint32_t f32_bits(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    return u;
+}
+
+uint16_t orc_bf16_sr(float x, uint32_t r16)
+{
+    uint32_t u = f32_bits(x);
+    if ((u & 0x7F800000u) == 0x7F800000u) {          /* Inf or NaN */
+        if (u & 0x007FFFFFu)
+            return (uint16_t)((u >> 16) | 0x0040u);   /* quiet NaN */
+        return (uint16_t)(u >> 16);
+    }
+    /* Adding r16 to the 16 dropped bits carries into the kept half with
+     * probability (dropped bits)/2^16: unbiased rounding of the magnitude. */
+    return (uint16_t)((u + (r16 & 0xFFFFu)) >> 16);
+}
+
+uint16_t orc_bf16_rne(float x)
+{
+    uint32_t u = f32_bits(x);
+    if ((u & 0x7F800000u) == 0x7F800000u) {
+        if (u & 0x007FFFFFu)
+            return (uint16_t)((u >> 16) | 0x0040u);
+        return (uint16_t)(u >> 16);
+    }
+    uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+double orc_bf16_to_f64(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Objective (Section 2): logistic classifier on M[v].M[u]                  */
+/* ------------------------------------------------------------------------ */
+double orc_sigmoid(double x)
+{
+    return 1.0 / (1.0 + exp(-x));
+}
+
+/* log(sigma(x)) without overflow. */
+static double log_sigmoid(double x)
+{
+    return x >= 0.0 ? -log1p(exp(-x)) : x - log1p(exp(x));
+}
+
+double orc_loss(double x, int b)
+{
+    return b ? -log_sigmoid(x) : -log_sigmoid(-x);
+}
+
+/* ------------------------------------------------------------------------ */
+/* UpdateEmbed (Algorithm 1) over the samples of one source                 */
+/* ------------------------------------------------------------------------ */
+static double row_get(const orc_emb* M, int64_t v, int32_t e)
+{
+    if (M->bf16)
+        return orc_bf16_to_f64(((const uint16_t*)M->rows)[v * M->d + e]);
+    return ((const double*)M->rows)[v * M->d + e];
+}
+
+int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                  double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch)
+{
+    const int32_t d = M->d;
+    double* s = (double*)malloc(sizeof(double) * (size_t)d);
+    double* m = (double*)malloc(sizeof(double) * (size_t)d);
+    int32_t done = 0;
+    for (int32_t e = 0; e < d; ++e)
+        s[e] = row_get(M, src, e);
+    for (int32_t t = 0; t <= k; ++t) {
+        int64_t u = samples[t];
+        if (u < 0 || u == src)
+            continue;
+        const double b = (t == 0) ? 1.0 : 0.0;
+        for (int32_t e = 0; e < d; ++e)
+            m[e] = row_get(M, u, e);
+        double x = 0.0;
+        for (int32_t e = 0; e < d; ++e)
+            x += s[e] * m[e];
+        const double score = (b - orc_sigmoid(x)) * lr;
+        for (int32_t e = 0; e < d; ++e)
+            s[e] += m[e] * score;
+        for (int32_t e = 0; e < d; ++e) {
+            double val = m[e] + s[e] * score;
+            if (M->bf16) {
+                uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, (uint32_t)t, e);
+                ((uint16_t*)M->rows)[u * d + e] = orc_bf16_sr((float)val, r);
+            } else {
+                ((double*)M->rows)[u * d + e] = val;
+            }
+        }
+        ++done;
+    }
+    for (int32_t e = 0; e < d; ++e) {
+        if (M->bf16) {
+            uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, 0xFFu, e);
+            ((uint16_t*)M->rows)[src * d + e] = orc_bf16_sr((float)s[e], r);
+        } else {
+            ((double*)M->rows)[src * d + e] = s[e];
+        }
+    }
+    free(s);
+    free(m);
+    return done;
+}
+
+int64_t orc_update_batch(orc_emb* M, int64_t nsrc, const int32_t* src,
+                         const int32_t* samples, int32_t k, double lr,
+                         uint64_t seed, int32_t level, uint32_t tag, int32_t epoch)
+{
+    int64_t done = 0;
+    for (int64_t i = 0; i < nsrc; ++i)
+        done += orc_visit(M, src[i], samples + i * (1 + k), k, lr, seed, level, tag, epoch);
+    return done;
+}
+
+/* ------------------------------------------------------------------------ */
+/* TrainInGPU (Algorithm 3), run sequentially                               */
+/* ------------------------------------------------------------------------ */
+int64_t orc_train(const int64_t* offsets, const int32_t* indices, int64_t n,
+                  orc_emb* M, int32_t epochs, double lr, int32_t k,
+                  uint64_t seed, int32_t level, uint32_t tag,
+                  int64_t src_lo, int64_t src_hi)
+{
+    int32_t samples[64];
+    int64_t done = 0;
+    for (int32_t j = 0; j < epochs; ++j) {
+        double f = 1.0 - (double)j / (double)epochs;
+        double lrj = lr * (f > 1e-4 ? f : 1e-4);
+        for (int64_t src = src_lo; src < src_hi; ++src) {
+            orc_draw_samples(offsets, indices, n, seed, level, tag, j, src, k, samples);
+            done += orc_visit(M, src, samples, k, lrj, seed, level, tag, j);
+        }
+    }
+    return done;
+}
+
+/* ------------------------------------------------------------------------ */
+/* MultiEdgeCollapse (Algorithm 4), one level                               */
+/* ------------------------------------------------------------------------ */
+int64_t orc_coarsen_map(const int64_t* offsets, const int32_t* indices, int64_t n,
+                        int32_t* map, int32_t* order_out)
+{
+    const int64_t nnz = offsets[n];
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t dv = offsets[v + 1] - offsets[v];
+        if (dv > maxdeg)
+            maxdeg = dv;
+    }
+    /* Counting sort on degree, larger first; equal degrees keep id order. */
+    int64_t* start = (int64_t*)calloc((size_t)maxdeg + 2, sizeof(int64_t));
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t v = 0; v < n; ++v)
+        start[maxdeg - (offsets[v + 1] - offsets[v])]++;
+    int64_t acc = 0;
+    for (int64_t b = 0; b <= maxdeg; ++b) {
+        int64_t c = start[b];
+        start[b] = acc;
+        acc += c;
+    }
+    for (int64_t v = 0; v < n; ++v)
+        order[start[maxdeg - (offsets[v + 1] - offsets[v])]++] = (int32_t)v;
+    free(start);
+
+    for (int64_t v = 0; v < n; ++v)
+        map[v] = -1;
+    int64_t cluster = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = order[i];
+        if (map[v] != -1)
+            continue;
+        map[v] = (int32_t)cluster++;
+        const int64_t dv = offsets[v + 1] - offsets[v];
+        for (int64_t p = offsets[v]; p < offsets[v + 1]; ++p) {
+            const int64_t u = indices[p];
+            const int64_t du = offsets[u + 1] - offsets[u];
+            /* hub^2 restriction: deg <= |E|/|V| written as deg * |V| <= |E| */
+            if (dv * n <= nnz || du * n <= nnz) {
+                if (map[u] == -1)
+                    map[u] = map[v];
+            }
+        }
+    }
+    if (order_out)
+        memcpy(order_out, order, sizeof(int32_t) * (size_t)n);
+    free(order);
+    return cluster;
+}
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_coarse_graph(const int64_t* offsets, const int32_t* indices, int64_t n,
+                         const int32_t* map, int64_t n_next,
+                         int64_t* off_out, int32_t* idx_out)
+{
+    const int64_t nnz = offsets[n];
+    uint64_t* pairs = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!pairs)
+        return -1;
+    int64_t m = 0;
+    for (int64_t v = 0; v < n; ++v)
+        for (int64_t p = offsets[v]; p < offsets[v + 1]; ++p) {
+            uint32_t a = (uint32_t)map[v], b = (uint32_t)map[indices[p]];
+            if (a != b)
+                pairs[m++] = ((uint64_t)a << 32) | b;
+        }
+    qsort(pairs, (size_t)m, sizeof(uint64_t), cmp_u64);
+    for (int64_t c = 0; c <= n_next; ++c)
+        off_out[c] = 0;
+    int64_t w = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (i > 0 && pairs[i] == pairs[i - 1])
+            continue;
+        off_out[(pairs[i] >> 32) + 1]++;
+        idx_out[w++] = (int32_t)(pairs[i] & 0xFFFFFFFFu);
+    }
+    for (int64_t c = 0; c < n_next; ++c)
+        off_out[c + 1] += off_out[c];
+    free(pairs);
+    return w;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Epoch distribution (Section 3): a share p spread evenly over the D       */
+/* levels, the rest geometrically with each coarser level getting twice    */
+/* the finer one's share.  Integer epochs: floors, then the remainder one   */
+/* each to the largest fractional parts (ties to the coarser level).        */
+/* ------------------------------------------------------------------------ */
+int32_t orc_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out)
+{
+    if (D <= 0 || e < 0 || !(p >= 0.0 && p <= 1.0))
+        return -1;
+    double* real = (double*)malloc(sizeof(double) * (size_t)D);
+    double denom = ldexp(1.0, D) - 1.0;
+    int64_t sum = 0;
+    for (int32_t i = 0; i < D; ++i) {
+        real[i] = p * (double)e / (double)D + (1.0 - p) * (double)e * ldexp(1.0, i) / denom;
+        e_out[i] = (int32_t)floor(real[i]);
+        sum += e_out[i];
+    }
+    int64_t rem = (int64_t)e - sum;
+    while (rem > 0) {
+        int32_t best = -1;
+        double bf = -1.0;
+        for (int32_t i = D - 1; i >= 0; --i) {
+            double f = real[i] - floor(real[i]);
+            if (f > bf) {
+                bf = f;
+                best = i;
+            }
+        }
+        e_out[best] += 1;
+        real[best] = floor(real[best]);   /* fractional part consumed */
+        --rem;
+    }
+    free(real);
+    return 0;
+}

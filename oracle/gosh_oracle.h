@@ -1,0 +1,103 @@
+/*
+ * GOSH CPU oracle (test infrastructure only).
+ *
+ * Plain, slow, single-threaded C11, FP64 for every real quantity.  It is the
+ * reference that the HIP path is checked against and shares no code with it.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it; the product path never does.
+ *
+ * Paper: "Boosting Graph Embedding on a Single GPU" (arXiv 2110.10049;
+ * GOSH).  Algorithms are numbered in the paper's order:
+ *   - UpdateEmbed .......... Algorithm 1 (Section 2)
+ *   - TrainInGPU ........... Algorithm 3 (Section 3.1), lr decay (Section 3)
+ *   - MultiEdgeCollapse .... Algorithm 4 (Section 4), CSR build (Section 4.1)
+ *   - epoch distribution ... Section 3 (calculateEpochs of Algorithm 2)
+ * Philox4x32-10 follows Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers:
+ * As Easy as 1, 2, 3", SC'11.
+ */
+#ifndef GOSH_ORACLE_H
+#define GOSH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x32 with 10 rounds: out = philox(ctr, key). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* One 128-bit block of the method's random stream.  Counter layout:
+ *   ctr = (src, epoch, (level & 0xFF) | tag << 8, kind << 24 | slot << 16 | block)
+ *   key = (seed low 32 bits, seed high 32 bits)
+ * kind 0 = sample draws, kind 1 = stochastic-rounding bits. */
+void orc_stream_block(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                      int64_t src, uint32_t kind, uint32_t slot, uint32_t block,
+                      uint32_t out[4]);
+
+/* Samples of one source (Algorithm 3): out[0] = positive (uniform neighbour,
+ * -1 when deg(src) = 0), out[1..k] = uniform negatives over [0, n). */
+void orc_draw_samples(const int64_t* offsets, const int32_t* indices, int64_t n,
+                      uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                      int64_t src, int32_t k, int32_t* out);
+
+/* 16 stochastic-rounding bits for element e of update slot `slot`. */
+uint32_t orc_sr_bits(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                     int64_t src, uint32_t slot, int32_t e);
+
+/* FP32 -> BF16 with stochastic rounding by 16 random bits. */
+uint16_t orc_bf16_sr(float x, uint32_t r16);
+/* FP32 -> BF16 round to nearest even. */
+uint16_t orc_bf16_rne(float x);
+double   orc_bf16_to_f64(uint16_t h);
+
+double orc_sigmoid(double x);
+/* -[b log s(x) + (1-b) log(1-s(x))], stable. */
+double orc_loss(double x, int b);
+
+/* Embedding storage.  bf16 == 0: rows are double[n*d]; bf16 != 0: rows are
+ * uint16_t[n*d] BF16 bit patterns, updated with stochastic rounding. */
+typedef struct {
+    void*   rows;
+    int32_t bf16;
+    int32_t d;
+} orc_emb;
+
+/* Applies the updates of one source visit with explicit samples (slot 0 is
+ * the positive, slots 1..k negatives; -1 or src itself = skipped).  Returns
+ * the number of UpdateEmbed calls executed. */
+int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                  double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch);
+
+/* Visits the listed sources in list order with explicit samples. */
+int64_t orc_update_batch(orc_emb* M, int64_t nsrc, const int32_t* src,
+                         const int32_t* samples, int32_t k, double lr,
+                         uint64_t seed, int32_t level, uint32_t tag, int32_t epoch);
+
+/* Sequential Algorithm 3: `epochs` passes, every source in [src_lo, src_hi)
+ * in ascending id order, lr' = lr * max(1 - j/epochs, 1e-4) at epoch j.
+ * Returns the number of executed UpdateEmbed calls. */
+int64_t orc_train(const int64_t* offsets, const int32_t* indices, int64_t n,
+                  orc_emb* M, int32_t epochs, double lr, int32_t k,
+                  uint64_t seed, int32_t level, uint32_t tag,
+                  int64_t src_lo, int64_t src_hi);
+
+/* One level of Algorithm 4 (MultiEdgeCollapse): fills map[n] and the
+ * processing order order[n] (may be NULL); returns |V_{i+1}|. */
+int64_t orc_coarsen_map(const int64_t* offsets, const int32_t* indices, int64_t n,
+                        int32_t* map, int32_t* order);
+
+/* Coarse graph of Section 4.1: deduplicated {(map v, map u) : map v != map u},
+ * rows ascending.  off_out has n_next+1 entries; idx_out must hold
+ * offsets[n] entries.  Returns nnz of the coarse graph, or -1 on OOM. */
+int64_t orc_coarse_graph(const int64_t* offsets, const int32_t* indices, int64_t n,
+                         const int32_t* map, int64_t n_next,
+                         int64_t* off_out, int32_t* idx_out);
+
+/* Epoch distribution over D levels (Section 3): e_out[i], i = 0 finest. */
+int32_t orc_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
