@@ -1,0 +1,182 @@
+/*
+ * gosh.h -- C ABI of the MI355X (gfx950) GOSH hot path.
+ *
+ * Method: "Boosting Graph Embedding on a Single GPU" (arXiv 2110.10049).
+ * A graph G_0 is coarsened level by level (MultiEdgeCollapse, Algorithm 4,
+ * Section 4); the levels are trained coarsest first (TrainInGPU,
+ * Algorithm 3, Section 3.1, built on UpdateEmbed, Algorithm 1) and each
+ * trained level is expanded onto the next finer one (ExpandEmbedding of
+ * Algorithm 2, Section 3).
+ *
+ * Conventions
+ *  - Every function returns gosh_status; none throws or aborts.  After a
+ *    failure, gosh_last_error(ctx) returns a message (valid until the next
+ *    call on that context).
+ *  - Pointers named `*_dev` or documented as device pointers are HIP device
+ *    memory owned by the caller unless stated otherwise; host pointers are
+ *    named `*_host`.
+ *  - All device work of a context is ordered on the context's stream
+ *    (gosh_ctx_create / gosh_set_stream).  Calls marked "asynchronous" only
+ *    enqueue; gosh_sync waits for them.
+ *  - A graph is a simple undirected graph stored as CSR with both
+ *    directions present: offsets[n+1] (int32 or int64, offsets[0] = 0,
+ *    non-decreasing, offsets[n] = nnz), indices[nnz] int32 in [0, n), rows
+ *    strictly ascending, no self-loops, symmetric.
+ *  - Embeddings are row-major [n, d] arrays of float32 or bfloat16.
+ *  - Random numbers come from Philox4x32-10 (Salmon et al., SC'11) keyed by
+ *    the context seed, with counter (src, epoch, level | tag << 8,
+ *    kind << 24 | slot << 16 | block): kind 0 draws the samples of a source,
+ *    kind 1 gives stochastic-rounding bits (slot t = update t of the visit,
+ *    slot 255 = the source row's write-back, block = element / 8).
+ */
+#ifndef GOSH_H
+#define GOSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GOSH_OK = 0,
+    GOSH_E_INVALID_ARG = 1,   /* bad argument (null pointer, size, d, k, lr ...) */
+    GOSH_E_BAD_GRAPH = 2,     /* CSR violates the graph convention above        */
+    GOSH_E_OOM = 3,           /* device allocation failed                       */
+    GOSH_E_CAP_EXCEEDED = 4,  /* the context's memory cap would be exceeded     */
+    GOSH_E_UNSUPPORTED = 5,   /* valid request this build does not implement    */
+    GOSH_E_DEVICE = 6         /* HIP runtime error                              */
+} gosh_status;
+
+typedef enum { GOSH_F32 = 0, GOSH_BF16 = 1 } gosh_dtype;
+
+typedef struct gosh_ctx gosh_ctx;
+typedef struct gosh_levels gosh_levels;
+
+/* Borrowed device view of a CSR graph (see conventions). */
+typedef struct {
+    int64_t n;                /* |V|                                         */
+    int64_t nnz;              /* stored directed entries = 2 |E|             */
+    const void* offsets;      /* device, n+1 entries of int32 or int64       */
+    int32_t offsets_is_i64;   /* 0: int32 offsets, 1: int64 offsets          */
+    const int32_t* indices;   /* device, nnz entries                         */
+} gosh_csr;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  `seed` keys every Philox
+ * stream.  `hip_stream` is a hipStream_t to order work on (NULL: the
+ * context creates its own).  `mem_cap_bytes` caps the device memory the
+ * library allocates for this context (0 = no cap); allocations beyond it
+ * fail with GOSH_E_CAP_EXCEEDED.  On success *out owns the context. */
+gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream,
+                            uint64_t mem_cap_bytes, gosh_ctx** out);
+gosh_status gosh_ctx_destroy(gosh_ctx* ctx);
+/* Orders subsequent work on `hip_stream` (NULL: the context's own stream). */
+gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream);
+/* Blocks until all work enqueued by the context has finished. */
+gosh_status gosh_sync(gosh_ctx* ctx);
+const char* gosh_last_error(const gosh_ctx* ctx);
+/* Bytes currently allocated by the library for this context. */
+gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes);
+/* Debug mode: when on, gosh_train visits sources strictly one after another
+ * in ascending id order (the sequential semantics of Algorithm 3 with its
+ * parallel loop run in order), so results are reproducible.  Default off:
+ * sources of an epoch run concurrently without locks (Section 3.1). */
+gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Checks `g` against the graph convention (Section 4.1: the method works on
+ * CSR).  check_symmetry != 0 also verifies that every (v,u) has (u,v).
+ * Synchronous.  GOSH_E_BAD_GRAPH names the first violated rule. */
+gosh_status gosh_validate_csr(gosh_ctx* ctx, const gosh_csr* g, int check_symmetry);
+
+/* MultiEdgeCollapse (Algorithm 4, Section 4).  Coarsens `g0` level by
+ * level: vertices are visited by decreasing degree (ties: ascending id); an
+ * unmarked vertex opens the next cluster id and takes every unmarked
+ * neighbour reached over an edge allowed by the hub^2 restriction
+ * (deg(v) <= nnz/n or deg(u) <= nnz/n); the coarse graph keeps one edge per
+ * pair of distinct clusters.  A level is appended, then coarsening stops
+ * when |V_{i+1}| < threshold or |V_{i+1}| > max_ratio * |V_i|.  The result
+ * equals the sequential algorithm exactly.
+ * `g0` is borrowed and must outlive *out.  Synchronous (level sizes drive
+ * allocation).  *out owns levels 1..D-1 (device CSR with the offset width
+ * of g0), the maps map_0..map_{D-2} and the cluster sizes. */
+gosh_status gosh_coarsen(gosh_ctx* ctx, const gosh_csr* g0, int64_t threshold,
+                         double max_ratio, gosh_levels** out);
+/* Wraps `g0` as a single-level hierarchy (no coarsening, D = 1). */
+gosh_status gosh_levels_single(gosh_ctx* ctx, const gosh_csr* g0, gosh_levels** out);
+gosh_status gosh_levels_destroy(gosh_levels* lv);
+gosh_status gosh_levels_count(const gosh_levels* lv, int32_t* D);
+gosh_status gosh_level_shape(const gosh_levels* lv, int32_t level, int64_t* n, int64_t* nnz);
+/* Device view of level `level` (valid while lv lives). */
+gosh_status gosh_level_csr(const gosh_levels* lv, int32_t level, gosh_csr* out);
+/* Device pointer to map_level (|V_level| int32 entries, values in
+ * [0, |V_{level+1}|)) and to the cluster sizes of level+1. */
+gosh_status gosh_level_map(const gosh_levels* lv, int32_t level, const int32_t** map_dev,
+                           const int32_t** clsz_dev);
+/* Copies a level to host memory; any of the three pointers may be NULL.
+ * offsets_host receives n+1 int64 values whatever the device width;
+ * map_host receives map_level (invalid for the coarsest level). Synchronous. */
+gosh_status gosh_level_copy_out(gosh_ctx* ctx, const gosh_levels* lv, int32_t level,
+                                int64_t* offsets_host, int32_t* indices_host,
+                                int32_t* map_host);
+
+/* ---------------------------------------------------------------- training */
+
+/* Epoch distribution (Section 3): a share p of the e epochs is spread evenly
+ * over the D levels and the rest geometrically, each coarser level getting
+ * twice the finer one's share; integer epochs by floor, the remainder one
+ * each to the largest fractional parts (ties to the coarser level).
+ * e_out[i] for level i (0 = finest).  Host function. */
+gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
+
+/* TrainInGPU (Algorithm 3) on level `level` of `lv`: `epochs` epochs run
+ * one after another; in epoch j every source vertex draws one positive
+ * (uniform neighbour; none if it has no neighbour) and k negatives (uniform
+ * over the level's vertices; one equal to the source is skipped) and
+ * applies UpdateEmbed (Algorithm 1) to each in turn with
+ * lr' = lr * max(1 - j/epochs, 1e-4): x = M[src].M[u],
+ * score = (b - sigmoid(x)) * lr', M[src] += score M[u], then
+ * M[u] += score M[src] with the updated source row.
+ * `emb` is a caller-owned device array [n_level, d] of `dt`, updated in
+ * place.  BF16 rows are widened to FP32 for the arithmetic and every
+ * written row is stochastically rounded back (sample rows once per update,
+ * the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
+ * lr finite and >= 0.  `tag` (24 bits) separates independent random
+ * streams.  If `updates_dev` is not NULL, the number of UpdateEmbed calls
+ * executed is added to *updates_dev (device uint64).  Asynchronous. */
+gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void* emb,
+                       gosh_dtype dt, int32_t d, int32_t epochs, float lr, int32_t k,
+                       uint32_t tag, uint64_t* updates_dev);
+
+/* ExpandEmbedding (Algorithm 2): fine[v] = coarse[map_{fine_level}[v]] for
+ * every vertex v of level fine_level.  coarse_emb: [n_{fine_level+1}, d],
+ * fine_emb: [n_{fine_level}, d], both device, same dtype.  Asynchronous. */
+gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_level,
+                         const void* coarse_emb, void* fine_emb, gosh_dtype dt, int32_t d);
+
+/* ---------------------------------------------------------------- test hooks */
+
+/* Writes the samples of every source of level `level` for epoch `epoch`:
+ * out_dev[src * (1+k) + 0] = positive (-1 if deg(src) = 0), [.. + t] =
+ * negative t.  Asynchronous. */
+gosh_status gosh_draw_samples(gosh_ctx* ctx, const gosh_levels* lv, int32_t level,
+                              int32_t epoch, int32_t k, uint32_t tag, int32_t* out_dev);
+
+/* UpdateEmbed over explicit samples: one source per entry of src_dev
+ * (nsrc entries), samples_dev[i * (1+k) + t] as in gosh_draw_samples (-1 =
+ * skip).  Rows are visited concurrently, so the result equals the
+ * sequential one only when no row is touched by two listed sources.
+ * Stochastic-rounding bits use (level, tag, epoch) and the source id.
+ * emb_dev holds n_rows rows; every index must be < n_rows.  Asynchronous. */
+gosh_status gosh_update_batch(gosh_ctx* ctx, void* emb_dev, gosh_dtype dt, int32_t d,
+                              int64_t n_rows, int32_t nsrc, const int32_t* src_dev,
+                              const int32_t* samples_dev, int32_t k, float lr,
+                              int32_t level, uint32_t tag, int32_t epoch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,416 @@
+// C ABI of the library (declared in include/gosh.h): argument checks, the
+// context with its capped caching allocator, and the level store.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gosh_internal.hpp"
+
+namespace gosh {
+
+// ---------------------------------------------------------------- allocator
+namespace {
+size_t bucket(size_t bytes) {
+    // 256 B granularity below 1 MiB, then 1/8 power-of-two steps
+    if (bytes < (1u << 20)) return (bytes + 255) & ~size_t(255);
+    size_t p = 1;
+    while (p < bytes) p <<= 1;
+    const size_t step = p >> 3;
+    return (bytes + step - 1) / step * step;
+}
+}  // namespace
+
+void* Ctx::alloc(size_t bytes) {
+    const size_t b = bucket(bytes == 0 ? 1 : bytes);
+    auto it = cache.lower_bound(b);
+    if (it != cache.end() && it->first <= b + b / 4) {
+        void* p = it->second;
+        live[p] = it->first;
+        cache.erase(it);
+        return p;
+    }
+    if (cap && in_use + b > cap) {
+        trim();
+        if (in_use + b > cap)
+            throw Error(GOSH_E_CAP_EXCEEDED, "device memory cap of " + std::to_string(cap) +
+                                                 " bytes would be exceeded");
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim();
+        e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(GOSH_E_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+    }
+    in_use += b;
+    live[p] = b;
+    return p;
+}
+
+void Ctx::free(void* p) {
+    if (!p) return;
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    cache.emplace(it->second, p);
+    live.erase(it);
+}
+
+void Ctx::trim() {
+    if (cache.empty()) return;
+    // blocks may still be in use by queued kernels of this stream
+    (void)hipStreamSynchronize(stream);
+    for (auto& kv : cache) {
+        (void)hipFree(kv.second);
+        in_use -= kv.first;
+    }
+    cache.clear();
+}
+
+}  // namespace gosh
+
+using gosh::Ctx;
+using gosh::Error;
+
+namespace {
+
+template <class F>
+gosh_status guarded(gosh_ctx* ctx, F&& f) {
+    try {
+        f();
+        if (ctx) ctx->c.err.clear();
+        return GOSH_OK;
+    } catch (const Error& e) {
+        if (ctx) ctx->c.err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->c.err = "host allocation failed";
+        return GOSH_E_OOM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->c.err = e.what();
+        return GOSH_E_DEVICE;
+    } catch (...) {
+        if (ctx) ctx->c.err = "unknown failure";
+        return GOSH_E_DEVICE;
+    }
+}
+
+void set_device(Ctx* c) { GOSH_HIP(hipSetDevice(c->device)); }
+
+const gosh::Level& level_of(const gosh_levels* lv, int32_t i) {
+    GOSH_REQUIRE(lv, GOSH_E_INVALID_ARG, "null levels");
+    GOSH_REQUIRE(i >= 0 && i < static_cast<int32_t>(lv->lv.size()), GOSH_E_INVALID_ARG,
+                 "level out of range");
+    return lv->lv[i];
+}
+
+void check_csr_view(const gosh_csr* g) {
+    GOSH_REQUIRE(g, GOSH_E_INVALID_ARG, "null csr");
+    GOSH_REQUIRE(g->n >= 0 && g->nnz >= 0, GOSH_E_INVALID_ARG, "negative csr size");
+    GOSH_REQUIRE(g->offsets, GOSH_E_INVALID_ARG, "null offsets");
+    GOSH_REQUIRE(g->nnz == 0 || g->indices, GOSH_E_INVALID_ARG, "null indices");
+    GOSH_REQUIRE(g->offsets_is_i64 || g->nnz <= INT32_MAX, GOSH_E_INVALID_ARG,
+                 "nnz beyond int32 needs int64 offsets");
+    GOSH_REQUIRE(g->n < INT32_MAX, GOSH_E_UNSUPPORTED, "vertex ids are int32");
+}
+
+}  // namespace
+
+extern "C" {
+
+gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream, uint64_t mem_cap_bytes,
+                            gosh_ctx** out) {
+    if (!out) return GOSH_E_INVALID_ARG;
+    *out = nullptr;
+    gosh_ctx* ctx = nullptr;
+    try {
+        ctx = new gosh_ctx();
+    } catch (...) {
+        return GOSH_E_OOM;
+    }
+    gosh_status st = guarded(ctx, [&] {
+        int count = 0;
+        GOSH_HIP(hipGetDeviceCount(&count));
+        GOSH_REQUIRE(device >= 0 && device < count, GOSH_E_INVALID_ARG, "no such HIP device");
+        Ctx* c = &ctx->c;
+        c->device = device;
+        c->seed = seed;
+        c->cap = mem_cap_bytes;
+        set_device(c);
+        if (hip_stream) {
+            c->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            GOSH_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+            c->stream = c->own_stream;
+        }
+        c->scratch = c->alloc(4096);
+        GOSH_HIP(hipMemsetAsync(c->scratch, 0, 4096, c->stream));
+    });
+    if (st != GOSH_OK) {
+        gosh_ctx_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return GOSH_OK;
+}
+
+gosh_status gosh_ctx_destroy(gosh_ctx* ctx) {
+    if (!ctx) return GOSH_OK;
+    Ctx* c = &ctx->c;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->live) (void)hipFree(kv.first);
+    for (auto& kv : c->cache) (void)hipFree(kv.second);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete ctx;
+    return GOSH_OK;
+}
+
+gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        Ctx* c = &ctx->c;
+        if (hip_stream) {
+            c->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            if (!c->own_stream) {
+                set_device(c);
+                GOSH_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+            }
+            c->stream = c->own_stream;
+        }
+    });
+}
+
+gosh_status gosh_sync(gosh_ctx* ctx) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        set_device(&ctx->c);
+        GOSH_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+const char* gosh_last_error(const gosh_ctx* ctx) {
+    if (!ctx) return "null context";
+    return ctx->c.err.c_str();
+}
+
+gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes) {
+    if (!ctx || !bytes) return GOSH_E_INVALID_ARG;
+    *bytes = ctx->c.in_use;
+    return GOSH_OK;
+}
+
+gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    ctx->c.deterministic = on != 0;
+    return GOSH_OK;
+}
+
+gosh_status gosh_validate_csr(gosh_ctx* ctx, const gosh_csr* g, int check_symmetry) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        check_csr_view(g);
+        set_device(&ctx->c);
+        gosh::validate_csr(&ctx->c, g, check_symmetry != 0);
+    });
+}
+
+gosh_status gosh_coarsen(gosh_ctx* ctx, const gosh_csr* g0, int64_t threshold, double max_ratio,
+                         gosh_levels** out) {
+    if (!ctx || !out) return GOSH_E_INVALID_ARG;
+    *out = nullptr;
+    gosh_levels* lv = nullptr;
+    gosh_status st = guarded(ctx, [&] {
+        check_csr_view(g0);
+        GOSH_REQUIRE(threshold >= 0, GOSH_E_INVALID_ARG, "threshold must be >= 0");
+        GOSH_REQUIRE(std::isfinite(max_ratio) && max_ratio > 0.0 && max_ratio <= 1.0, GOSH_E_INVALID_ARG,
+                     "max_ratio must be in (0, 1]");
+        set_device(&ctx->c);
+        gosh::validate_csr(&ctx->c, g0, false);
+        lv = new gosh_levels();
+        lv->ctx = &ctx->c;
+        gosh::coarsen(&ctx->c, g0, threshold, max_ratio, lv);
+        GOSH_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+    if (st != GOSH_OK) {
+        if (lv) gosh_levels_destroy(lv);
+        return st;
+    }
+    *out = lv;
+    return GOSH_OK;
+}
+
+gosh_status gosh_levels_single(gosh_ctx* ctx, const gosh_csr* g0, gosh_levels** out) {
+    if (!ctx || !out) return GOSH_E_INVALID_ARG;
+    *out = nullptr;
+    gosh_levels* lv = nullptr;
+    gosh_status st = guarded(ctx, [&] {
+        check_csr_view(g0);
+        set_device(&ctx->c);
+        gosh::validate_csr(&ctx->c, g0, false);
+        lv = new gosh_levels();
+        lv->ctx = &ctx->c;
+        gosh::Level L;
+        L.n = g0->n;
+        L.nnz = g0->nnz;
+        L.off64 = g0->offsets_is_i64 != 0;
+        L.offsets = g0->offsets;
+        L.indices = g0->indices;
+        L.n_deg0 = gosh::count_isolated(&ctx->c, L);
+        lv->lv.push_back(L);
+    });
+    if (st != GOSH_OK) {
+        if (lv) gosh_levels_destroy(lv);
+        return st;
+    }
+    *out = lv;
+    return GOSH_OK;
+}
+
+gosh_status gosh_levels_destroy(gosh_levels* lv) {
+    if (!lv) return GOSH_OK;
+    if (lv->ctx) {
+        (void)hipSetDevice(lv->ctx->device);
+        for (auto& L : lv->lv) gosh::free_level(lv->ctx, L);
+    }
+    delete lv;
+    return GOSH_OK;
+}
+
+gosh_status gosh_levels_count(const gosh_levels* lv, int32_t* D) {
+    if (!lv || !D) return GOSH_E_INVALID_ARG;
+    *D = static_cast<int32_t>(lv->lv.size());
+    return GOSH_OK;
+}
+
+gosh_status gosh_level_shape(const gosh_levels* lv, int32_t level, int64_t* n, int64_t* nnz) {
+    if (!lv || level < 0 || level >= static_cast<int32_t>(lv->lv.size())) return GOSH_E_INVALID_ARG;
+    if (n) *n = lv->lv[level].n;
+    if (nnz) *nnz = lv->lv[level].nnz;
+    return GOSH_OK;
+}
+
+gosh_status gosh_level_csr(const gosh_levels* lv, int32_t level, gosh_csr* out) {
+    if (!lv || !out || level < 0 || level >= static_cast<int32_t>(lv->lv.size())) return GOSH_E_INVALID_ARG;
+    const gosh::Level& L = lv->lv[level];
+    out->n = L.n;
+    out->nnz = L.nnz;
+    out->offsets = L.offsets;
+    out->offsets_is_i64 = L.off64 ? 1 : 0;
+    out->indices = L.indices;
+    return GOSH_OK;
+}
+
+gosh_status gosh_level_map(const gosh_levels* lv, int32_t level, const int32_t** map_dev,
+                           const int32_t** clsz_dev) {
+    if (!lv || level < 0 || level + 1 >= static_cast<int32_t>(lv->lv.size())) return GOSH_E_INVALID_ARG;
+    if (map_dev) *map_dev = lv->lv[level].map;
+    if (clsz_dev) *clsz_dev = lv->lv[level].clsz;
+    return GOSH_OK;
+}
+
+gosh_status gosh_level_copy_out(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, int64_t* offsets_host,
+                                int32_t* indices_host, int32_t* map_host) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        const gosh::Level& L = level_of(lv, level);
+        Ctx* c = &ctx->c;
+        set_device(c);
+        if (offsets_host) {
+            if (L.off64) {
+                GOSH_HIP(hipMemcpyAsync(offsets_host, L.offsets, 8 * (L.n + 1), hipMemcpyDeviceToHost, c->stream));
+            } else {
+                std::vector<int32_t> tmp(L.n + 1);
+                GOSH_HIP(hipMemcpyAsync(tmp.data(), L.offsets, 4 * (L.n + 1), hipMemcpyDeviceToHost, c->stream));
+                GOSH_HIP(hipStreamSynchronize(c->stream));
+                for (int64_t i = 0; i <= L.n; ++i) offsets_host[i] = tmp[i];
+            }
+        }
+        if (indices_host && L.nnz > 0)
+            GOSH_HIP(hipMemcpyAsync(indices_host, L.indices, 4 * L.nnz, hipMemcpyDeviceToHost, c->stream));
+        if (map_host) {
+            GOSH_REQUIRE(L.map, GOSH_E_INVALID_ARG, "the coarsest level has no map");
+            if (L.n > 0)
+                GOSH_HIP(hipMemcpyAsync(map_host, L.map, 4 * L.n, hipMemcpyDeviceToHost, c->stream));
+        }
+        GOSH_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out) {
+    if (!e_out || D <= 0 || e < 0 || !(p >= 0.0 && p <= 1.0)) return GOSH_E_INVALID_ARG;
+    std::vector<double> real(D);
+    const double denom = std::ldexp(1.0, D) - 1.0;
+    int64_t sum = 0;
+    for (int32_t i = 0; i < D; ++i) {
+        real[i] = p * e / D + (1.0 - p) * e * std::ldexp(1.0, i) / denom;
+        e_out[i] = static_cast<int32_t>(std::floor(real[i]));
+        sum += e_out[i];
+    }
+    for (int64_t rem = static_cast<int64_t>(e) - sum; rem > 0; --rem) {
+        int32_t best = D - 1;
+        double bf = -1.0;
+        for (int32_t i = D - 1; i >= 0; --i) {
+            const double f = real[i] - std::floor(real[i]);
+            if (f > bf) {
+                bf = f;
+                best = i;
+            }
+        }
+        e_out[best] += 1;
+        real[best] = std::floor(real[best]);
+    }
+    return GOSH_OK;
+}
+
+gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void* emb, gosh_dtype dt,
+                       int32_t d, int32_t epochs, float lr, int32_t k, uint32_t tag, uint64_t* updates_dev) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        const gosh::Level& L = level_of(lv, level);
+        set_device(&ctx->c);
+        gosh::train_level(&ctx->c, L, level, emb, dt, d, epochs, lr, k, tag, updates_dev);
+    });
+}
+
+gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_level, const void* coarse_emb,
+                         void* fine_emb, gosh_dtype dt, int32_t d) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        const gosh::Level& L = level_of(lv, fine_level);
+        GOSH_REQUIRE(fine_level + 1 < static_cast<int32_t>(lv->lv.size()), GOSH_E_INVALID_ARG,
+                     "fine_level must have a coarser level");
+        set_device(&ctx->c);
+        gosh::prolong_copy(&ctx->c, L, coarse_emb, fine_emb, dt, d);
+    });
+}
+
+gosh_status gosh_draw_samples(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, int32_t epoch, int32_t k,
+                              uint32_t tag, int32_t* out_dev) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        const gosh::Level& L = level_of(lv, level);
+        GOSH_REQUIRE(tag < (1u << 24), GOSH_E_INVALID_ARG, "tag must fit in 24 bits");
+        set_device(&ctx->c);
+        gosh::draw_samples(&ctx->c, L, level, epoch, k, tag, out_dev);
+    });
+}
+
+gosh_status gosh_update_batch(gosh_ctx* ctx, void* emb_dev, gosh_dtype dt, int32_t d, int64_t n_rows,
+                              int32_t nsrc, const int32_t* src_dev, const int32_t* samples_dev, int32_t k,
+                              float lr, int32_t level, uint32_t tag, int32_t epoch) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        set_device(&ctx->c);
+        gosh::update_batch(&ctx->c, emb_dev, dt, d, n_rows, nsrc, src_dev, samples_dev, k, lr, level, tag,
+                           epoch);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations of the gfx950 GOSH library: context, device memory
+// accounting, level store and the device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gosh.h"
+
+namespace gosh {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    gosh_status code;
+    Error(gosh_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define GOSH_HIP(call)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::gosh::Error(GOSH_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GOSH_REQUIRE(cond, code, msg)                                                      \
+    do {                                                                                   \
+        if (!(cond)) throw ::gosh::Error(code, msg);                                       \
+    } while (0)
+
+// ---------------------------------------------------------------- context
+struct Ctx {
+    int device = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    uint64_t cap = 0;          // 0 = unlimited
+    uint64_t in_use = 0;       // bytes held by live allocations and the cache
+    bool deterministic = false;
+    std::string err;
+    // Size-bucketed cache of freed device blocks, reused before hipMalloc.
+    std::multimap<size_t, void*> cache;
+    std::map<void*, size_t> live;
+    // small device scratch for counters and flags
+    void* scratch = nullptr;   // 4 KiB
+
+    void* alloc(size_t bytes);
+    void free(void* p);
+    void trim();               // releases cached blocks
+};
+
+// RAII device buffer tied to a context
+template <class T>
+struct DevBuf {
+    Ctx* ctx = nullptr;
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(Ctx* c, size_t count) : ctx(c), n(count) {
+        p = static_cast<T*>(c->alloc(count * sizeof(T)));
+    }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : ctx(o.ctx), p(o.p), n(o.n) { o.p = nullptr; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        reset();
+        ctx = o.ctx; p = o.p; n = o.n; o.p = nullptr;
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p && ctx) ctx->free(p);
+        p = nullptr;
+        n = 0;
+    }
+    T* release() { T* q = p; p = nullptr; n = 0; return q; }
+};
+
+// ---------------------------------------------------------------- levels
+struct Level {
+    int64_t n = 0, nnz = 0;
+    bool off64 = false;
+    const void* offsets = nullptr;     // device
+    const int32_t* indices = nullptr;  // device
+    void* own_offsets = nullptr;       // owned storage (levels >= 1)
+    int32_t* own_indices = nullptr;
+    int32_t* map = nullptr;            // map to level+1 (owned), null on the coarsest
+    int32_t* clsz = nullptr;           // sizes of level+1's clusters (owned)
+    int64_t n_deg0 = 0;                // vertices without neighbours
+};
+
+}  // namespace gosh
+
+struct gosh_ctx {
+    gosh::Ctx c;
+};
+
+struct gosh_levels {
+    gosh::Ctx* ctx = nullptr;
+    std::vector<gosh::Level> lv;
+};
+
+namespace gosh {
+
+// ---------------------------------------------------------------- host entry points
+// (implemented in coarsen.hip / train.hip / prolong.hip)
+void validate_csr(Ctx* c, const gosh_csr* g, bool symmetry);
+void coarsen(Ctx* c, const gosh_csr* g0, int64_t threshold, double ratio, gosh_levels* out);
+int64_t count_isolated(Ctx* c, const Level& L);
+void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d,
+                 int epochs, float lr, int k, uint32_t tag, uint64_t* updates_dev);
+void draw_samples(Ctx* c, const Level& L, int32_t level, int32_t epoch, int k, uint32_t tag,
+                  int32_t* out);
+void update_batch(Ctx* c, void* emb, gosh_dtype dt, int d, int64_t n_rows, int nsrc,
+                  const int32_t* src, const int32_t* samples, int k, float lr, int32_t level,
+                  uint32_t tag, int32_t epoch);
+void prolong_copy(Ctx* c, const Level& fine, const void* coarse, void* fine_emb, gosh_dtype dt,
+                  int d);
+void free_level(Ctx* c, Level& L);
+
+}  // namespace gosh

@@ -1,0 +1,264 @@
+// Device-wide scans and a stable LSD radix sort for gfx950 (wave64).
+#include "primitives.hpp"
+
+#include "device_util.hpp"
+
+namespace gosh {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <ScanOp OP>
+__host__ __device__ __forceinline__ int64_t apply(int64_t a, int64_t b) {
+    if constexpr (OP == ScanOp::Sum) return a + b;
+    else return a > b ? a : b;
+}
+
+// Inclusive scan across a wave64.
+template <ScanOp OP>
+__device__ __forceinline__ int64_t wave_inclusive(int64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v = apply<OP>(v, t);
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the block; *total receives
+// the block total.
+template <ScanOp OP>
+__device__ __forceinline__ int64_t block_exclusive(int64_t v, int64_t* total) {
+    __shared__ int64_t wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t inc = wave_inclusive<OP>(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int64_t before = 0;
+    int64_t all = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / 64; ++i) {
+        if (i < w) before = apply<OP>(before, wsum[i]);
+        all = apply<OP>(all, wsum[i]);
+    }
+    __syncthreads();
+    *total = all;
+    const int64_t ex_in_wave = __shfl_up(inc, 1, 64);
+    return apply<OP>(before, lane ? ex_in_wave : 0);
+}
+
+template <class T, ScanOp OP>
+__global__ __launch_bounds__(kScanThreads) void k_tile_reduce(const T* in, int64_t n, int64_t* part) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i * kScanThreads + threadIdx.x;
+        if (idx < n) acc = apply<OP>(acc, static_cast<int64_t>(in[idx]));
+    }
+    int64_t total;
+    block_exclusive<OP>(acc, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Scans one tile per block (blocked arrangement: thread t owns items
+// [t*kScanItems, (t+1)*kScanItems) of the tile), adding prefix[block].
+template <class T, ScanOp OP>
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const T* in, int64_t* out, int64_t n,
+                                                             const int64_t* prefix, int inclusive) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    const int64_t start = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = start + i;
+        v[i] = idx < n ? static_cast<int64_t>(in[idx]) : 0;
+        acc = apply<OP>(acc, v[i]);
+    }
+    int64_t total;
+    int64_t run = block_exclusive<OP>(acc, &total);
+    if (prefix) run = apply<OP>(prefix[blockIdx.x], run);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = start + i;
+        const int64_t nxt = apply<OP>(run, v[i]);
+        if (idx < n) out[idx] = inclusive ? nxt : run;
+        run = nxt;
+    }
+}
+
+template <class T, ScanOp OP>
+void scan_launch(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive) {
+    const int64_t nb = ceil_div(n, kScanTile);
+    if (nb == 1) {
+        hipLaunchKernelGGL((k_tile_scan<T, OP>), dim3(1), dim3(kScanThreads), 0, c->stream, in, out,
+                           n, nullptr, inclusive ? 1 : 0);
+        GOSH_HIP(hipGetLastError());
+        return;
+    }
+    DevBuf<int64_t> part(c, nb);
+    hipLaunchKernelGGL((k_tile_reduce<T, OP>), dim3(nb), dim3(kScanThreads), 0, c->stream, in, n,
+                       part.p);
+    GOSH_HIP(hipGetLastError());
+    scan_launch<int64_t, OP>(c, part.p, part.p, nb, false);
+    hipLaunchKernelGGL((k_tile_scan<T, OP>), dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, n,
+                       part.p, inclusive ? 1 : 0);
+    GOSH_HIP(hipGetLastError());
+}
+
+template <class T, ScanOp OP>
+void scan_impl(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int64_t* total_host) {
+    if (n <= 0) {
+        if (total_host) *total_host = 0;
+        return;
+    }
+    // The last input is fetched before the scan because `out` may alias `in`.
+    T last_in{};
+    if (total_host && !inclusive)
+        GOSH_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    scan_launch<T, OP>(c, in, out, n, inclusive);
+    if (total_host) {
+        int64_t last_out = 0;
+        GOSH_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                c->stream));
+        GOSH_HIP(hipStreamSynchronize(c->stream));
+        *total_host = inclusive ? last_out : apply<OP>(last_out, static_cast<int64_t>(last_in));
+    }
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 32;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadix = 256;
+constexpr int kWaves = kSortThreads / 64;
+
+template <class K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, int64_t n, int shift,
+                                                             int64_t* hist, int64_t nb) {
+    __shared__ int cnt[kRadix];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t idx = base + i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[static_cast<int>((keys[idx] >> shift) & (kRadix - 1))], 1);
+    }
+    __syncthreads();
+    hist[static_cast<int64_t>(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Scatters one tile: keys of equal digit keep their input order (stable).
+// The tile is consumed in rounds of 256 consecutive keys; inside a round a
+// key's rank among equal digits is (earlier waves' counts) + (earlier lanes
+// of its own wave with the same digit, found with 8 ballots).
+template <class K, bool VALS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K* keys_out,
+                                                                const uint32_t* vals,
+                                                                uint32_t* vals_out, int64_t n,
+                                                                int shift, const int64_t* offs,
+                                                                int64_t nb) {
+    __shared__ int64_t base_off[kRadix];
+    __shared__ int wave_cnt[kWaves][kRadix];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base_off[tid] = offs[static_cast<int64_t>(tid) * nb + blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) wave_cnt[i][tid] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tile = static_cast<int64_t>(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = tile + static_cast<int64_t>(r) * kSortThreads + tid;
+        const bool valid = idx < n;
+        K key = valid ? keys[idx] : K(0);
+        uint32_t val = (VALS && valid) ? vals[idx] : 0u;
+        const int digit = static_cast<int>((key >> shift) & (kRadix - 1));
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (digit >> b) & 1;
+            const uint64_t m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt_mask);
+        const bool leader = valid && rank == 0;
+        if (leader) wave_cnt[w][digit] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int64_t pos = base_off[digit] + rank;
+            for (int i = 0; i < w; ++i) pos += wave_cnt[i][digit];
+            keys_out[pos] = key;
+            if constexpr (VALS) vals_out[pos] = val;
+        }
+        __syncthreads();
+        {
+            int add = 0;
+#pragma unroll
+            for (int i = 0; i < kWaves; ++i) {
+                add += wave_cnt[i][tid];
+                wave_cnt[i][tid] = 0;
+            }
+            base_off[tid] += add;
+        }
+        __syncthreads();
+        if (tile + static_cast<int64_t>(r + 1) * kSortThreads >= n) break;
+    }
+}
+
+template <class K, bool VALS>
+void radix_sort_impl(Ctx* c, K* keys, K* keys_tmp, uint32_t* vals, uint32_t* vals_tmp, int64_t n,
+                     int bits) {
+    if (n <= 1 || bits <= 0) return;
+    const int64_t nb = ceil_div(n, kSortTile);
+    DevBuf<int64_t> hist(c, static_cast<size_t>(nb) * kRadix);
+    K* src = keys;
+    K* dst = keys_tmp;
+    uint32_t* vsrc = vals;
+    uint32_t* vdst = vals_tmp;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL((k_radix_hist<K>), dim3(nb), dim3(kSortThreads), 0, c->stream, src, n,
+                           shift, hist.p, nb);
+        GOSH_HIP(hipGetLastError());
+        scan_impl<int64_t, ScanOp::Sum>(c, hist.p, hist.p, nb * kRadix, false, nullptr);
+        hipLaunchKernelGGL((k_radix_scatter<K, VALS>), dim3(nb), dim3(kSortThreads), 0, c->stream,
+                           src, dst, vsrc, vdst, n, shift, hist.p, nb);
+        GOSH_HIP(hipGetLastError());
+        std::swap(src, dst);
+        std::swap(vsrc, vdst);
+    }
+    if (src != keys) {
+        GOSH_HIP(hipMemcpyAsync(keys, src, sizeof(K) * n, hipMemcpyDeviceToDevice, c->stream));
+        if (VALS)
+            GOSH_HIP(hipMemcpyAsync(vals, vsrc, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
+                                    c->stream));
+    }
+}
+
+}  // namespace
+
+void scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n, bool inclusive, ScanOp op,
+              int64_t* total_host) {
+    if (op == ScanOp::Sum) scan_impl<int64_t, ScanOp::Sum>(c, in, out, n, inclusive, total_host);
+    else scan_impl<int64_t, ScanOp::Max>(c, in, out, n, inclusive, total_host);
+}
+
+void scan_i32_to_i64(Ctx* c, const int32_t* in, int64_t* out, int64_t n, int64_t* total_host) {
+    scan_impl<int32_t, ScanOp::Sum>(c, in, out, n, false, total_host);
+}
+
+void radix_sort_u32(Ctx* c, uint32_t* keys, uint32_t* keys_tmp, uint32_t* vals,
+                    uint32_t* vals_tmp, int64_t n, int bits) {
+    if (vals) radix_sort_impl<uint32_t, true>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
+    else radix_sort_impl<uint32_t, false>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+}
+
+void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits) {
+    radix_sort_impl<uint64_t, false>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+}
+
+}  // namespace gosh

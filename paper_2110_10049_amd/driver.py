@@ -1,0 +1,58 @@
+"""Algorithm 2 (Section 3) over the C ABI: coarsen, initialise the coarsest
+rows, train every level from the coarsest to the original graph with its
+share of the epochs, and expand each trained level onto the next finer one.
+
+Orchestration only: coarsening, training and expansion run in libgosh.so.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from . import gosh as G
+
+
+@dataclass
+class EmbedConfig:
+    d: int = 128
+    epochs: int = 600          # e: total epochs over all levels (Algorithm 3 passes)
+    p: float = 0.3             # smoothing ratio of the epoch distribution
+    lr: float = 0.045
+    k: int = 3                 # negatives per source (n_s)
+    dtype: torch.dtype = torch.float32
+    threshold: int = 100
+    max_ratio: float = 0.8
+    tag: int = 0
+
+
+@dataclass
+class EmbedResult:
+    emb: torch.Tensor
+    sizes: list
+    schedule: list
+    updates: int = 0
+    levels: object = None
+    timings: dict = field(default_factory=dict)
+
+
+def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels | None = None,
+          coarsen: bool = True) -> EmbedResult:
+    """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level."""
+    if levels is None:
+        levels = G.gosh_coarsen(ctx, g0, cfg.threshold, cfg.max_ratio) if coarsen else G.gosh_levels_single(ctx, g0)
+    D = levels.count()
+    sizes = levels.sizes()
+    sched = G.gosh_epoch_schedule(cfg.epochs, cfg.p, D)
+    dev = f"cuda:{ctx.device}"
+    M = init_fn(sizes[-1], cfg.d)
+    if M.dtype != cfg.dtype or tuple(M.shape) != (sizes[-1], cfg.d):
+        raise ValueError("init_fn returned a wrong shape or dtype")
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    for i in range(D - 1, -1, -1):
+        G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
+        if i > 0:
+            fine = torch.empty((sizes[i - 1], cfg.d), dtype=cfg.dtype, device=dev)
+            G.gosh_prolong(ctx, levels, i - 1, M, fine)
+            M = fine
+    return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels)

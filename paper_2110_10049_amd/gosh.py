@@ -1,0 +1,275 @@
+"""ctypes binding of libgosh.so (the C ABI in include/gosh.h).
+
+Argument marshalling only: torch device tensors are passed by data_ptr(),
+the current torch stream is handed to the context, and every status code
+other than GOSH_OK raises GoshError with the library's message.  There is no
+fallback: if libgosh.so is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgosh.so")
+
+GOSH_F32, GOSH_BF16 = 0, 1
+STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_BAD_GRAPH", 3: "E_OOM", 4: "E_CAP_EXCEEDED",
+          5: "E_UNSUPPORTED", 6: "E_DEVICE"}
+
+
+class GoshError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class gosh_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("offsets", C.c_void_p),
+                ("offsets_is_i64", C.c_int32), ("indices", C.c_void_p)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_P = C.c_void_p
+_SIGNATURES = [
+    ("gosh_ctx_create", C.c_int, [C.c_int, C.c_uint64, _P, C.c_uint64, C.POINTER(_P)]),
+    ("gosh_ctx_destroy", C.c_int, [_P]),
+    ("gosh_set_stream", C.c_int, [_P, _P]),
+    ("gosh_sync", C.c_int, [_P]),
+    ("gosh_last_error", C.c_char_p, [_P]),
+    ("gosh_mem_in_use", C.c_int, [_P, C.POINTER(C.c_uint64)]),
+    ("gosh_set_deterministic", C.c_int, [_P, C.c_int]),
+    ("gosh_validate_csr", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int]),
+    ("gosh_coarsen", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int64, C.c_double, C.POINTER(_P)]),
+    ("gosh_levels_single", C.c_int, [_P, C.POINTER(gosh_csr), C.POINTER(_P)]),
+    ("gosh_levels_destroy", C.c_int, [_P]),
+    ("gosh_levels_count", C.c_int, [_P, C.POINTER(C.c_int32)]),
+    ("gosh_level_shape", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("gosh_level_csr", C.c_int, [_P, C.c_int32, C.POINTER(gosh_csr)]),
+    ("gosh_level_map", C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
+    ("gosh_level_copy_out", C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
+    ("gosh_epoch_schedule", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+    ("gosh_train", C.c_int, [_P, _P, C.c_int32, _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
+                             C.c_int32, C.c_uint32, _P]),
+    ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32]),
+    ("gosh_draw_samples", C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P]),
+    ("gosh_update_batch", C.c_int, [_P, _P, C.c_int, C.c_int32, C.c_int64, C.c_int32, _P, _P,
+                                    C.c_int32, C.c_float, C.c_int32, C.c_uint32, C.c_int32]),
+]
+EXPORTS = [s[0] for s in _SIGNATURES]
+
+
+def lib():
+    """Loads libgosh.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2110_10049_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return GOSH_F32
+    if t.dtype == torch.bfloat16:
+        return GOSH_BF16
+    raise TypeError("embeddings are float32 or bfloat16")
+
+
+def _dev(t: torch.Tensor, dtype=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A gosh_ctx bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, seed: int = 0, mem_cap: int = 0, stream=None):
+        self._L = lib()
+        self.device = device
+        h = C.c_void_p()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._check_raw(self._L.gosh_ctx_create(device, seed, C.c_void_p(stream.cuda_stream), mem_cap,
+                                                C.byref(h)), None)
+        self.h = h
+        self.stream = stream
+
+    def _check_raw(self, st, h):
+        if st != 0:
+            msg = self._L.gosh_last_error(h).decode() if h is not None else "context creation failed"
+            raise GoshError(st, msg)
+
+    def check(self, st):
+        if st != 0:
+            raise GoshError(st, self._L.gosh_last_error(self.h).decode())
+
+    def use_current_stream(self):
+        s = torch.cuda.current_stream(self.device)
+        self.check(self._L.gosh_set_stream(self.h, C.c_void_p(s.cuda_stream)))
+        self.stream = s
+
+    def sync(self):
+        self.check(self._L.gosh_sync(self.h))
+
+    def mem_in_use(self) -> int:
+        v = C.c_uint64()
+        self.check(self._L.gosh_mem_in_use(self.h, C.byref(v)))
+        return v.value
+
+    def set_deterministic(self, on: bool):
+        self.check(self._L.gosh_set_deterministic(self.h, 1 if on else 0))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._L.gosh_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CSR:
+    """Keeps device tensors alive behind a gosh_csr view."""
+
+    def __init__(self, offsets: torch.Tensor, indices: torch.Tensor):
+        if offsets.dtype not in (torch.int32, torch.int64):
+            raise TypeError("offsets must be int32 or int64")
+        _dev(offsets, name="offsets")
+        _dev(indices, torch.int32, "indices")
+        self.offsets, self.indices = offsets, indices
+        self.view = gosh_csr(offsets.numel() - 1, indices.numel(), offsets.data_ptr(),
+                             1 if offsets.dtype == torch.int64 else 0, indices.data_ptr())
+
+    @classmethod
+    def from_numpy(cls, offsets, indices, device="cuda", off64=False):
+        o = torch.as_tensor(offsets, dtype=torch.int64 if off64 else torch.int32).to(device)
+        i = torch.as_tensor(indices, dtype=torch.int32).to(device)
+        return cls(o.contiguous(), i.contiguous())
+
+
+class Levels:
+    """A gosh_levels hierarchy; keeps the level-0 CSR alive."""
+
+    def __init__(self, ctx: Context, handle: C.c_void_p, g0: CSR):
+        self.ctx, self.h, self.g0 = ctx, handle, g0
+
+    def count(self) -> int:
+        D = C.c_int32()
+        self.ctx.check(lib().gosh_levels_count(self.h, C.byref(D)))
+        return D.value
+
+    def shape(self, level: int):
+        n, nnz = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().gosh_level_shape(self.h, level, C.byref(n), C.byref(nnz)))
+        return n.value, nnz.value
+
+    def sizes(self):
+        return [self.shape(i)[0] for i in range(self.count())]
+
+    def csr(self, level: int) -> gosh_csr:
+        out = gosh_csr()
+        self.ctx.check(lib().gosh_level_csr(self.h, level, C.byref(out)))
+        return out
+
+    def copy_out(self, level: int, want_map=True):
+        import numpy as np
+        n, nnz = self.shape(level)
+        off = np.zeros(n + 1, np.int64)
+        idx = np.zeros(max(nnz, 1), np.int32)
+        mp = np.zeros(max(n, 1), np.int32) if want_map else None
+        self.ctx.check(lib().gosh_level_copy_out(
+            self.ctx.h, self.h, level, off.ctypes.data, idx.ctypes.data,
+            mp.ctypes.data if mp is not None else None))
+        return off, idx[:nnz], (mp[:n] if mp is not None else None)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().gosh_levels_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ entry points
+def gosh_validate_csr(ctx: Context, g: CSR, check_symmetry: bool = True):
+    ctx.check(lib().gosh_validate_csr(ctx.h, C.byref(g.view), 1 if check_symmetry else 0))
+
+
+def gosh_coarsen(ctx: Context, g0: CSR, threshold: int = 100, max_ratio: float = 0.8) -> Levels:
+    h = C.c_void_p()
+    ctx.check(lib().gosh_coarsen(ctx.h, C.byref(g0.view), threshold, max_ratio, C.byref(h)))
+    return Levels(ctx, h, g0)
+
+
+def gosh_levels_single(ctx: Context, g0: CSR) -> Levels:
+    h = C.c_void_p()
+    ctx.check(lib().gosh_levels_single(ctx.h, C.byref(g0.view), C.byref(h)))
+    return Levels(ctx, h, g0)
+
+
+def gosh_epoch_schedule(e: int, p: float, D: int):
+    out = (C.c_int32 * D)()
+    st = lib().gosh_epoch_schedule(e, p, D, out)
+    if st != 0:
+        raise GoshError(st, "bad schedule arguments")
+    return list(out)
+
+
+def gosh_train(ctx: Context, lv: Levels, level: int, emb: torch.Tensor, epochs: int, lr: float, k: int,
+               tag: int = 0, updates: torch.Tensor | None = None):
+    n, _ = lv.shape(level)
+    if emb.dim() != 2 or emb.shape[0] != n:
+        raise ValueError(f"embedding must be [{n}, d]")
+    e = _dev(emb, name="emb")
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    ctx.check(lib().gosh_train(ctx.h, lv.h, level, e, _dtype_code(emb), emb.shape[1], epochs, lr, k, tag, u))
+
+
+def gosh_prolong(ctx: Context, lv: Levels, fine_level: int, coarse: torch.Tensor, fine: torch.Tensor):
+    nf, _ = lv.shape(fine_level)
+    nc, _ = lv.shape(fine_level + 1)
+    if coarse.shape != (nc, fine.shape[1]) or fine.shape[0] != nf or coarse.dtype != fine.dtype:
+        raise ValueError("prolong shapes/dtypes do not match the levels")
+    ctx.check(lib().gosh_prolong(ctx.h, lv.h, fine_level, _dev(coarse, name="coarse"), _dev(fine, name="fine"),
+                                 _dtype_code(fine), fine.shape[1]))
+
+
+def gosh_draw_samples(ctx: Context, lv: Levels, level: int, epoch: int, k: int, tag: int = 0) -> torch.Tensor:
+    n, _ = lv.shape(level)
+    out = torch.empty((n, 1 + k), dtype=torch.int32, device=f"cuda:{ctx.device}")
+    ctx.check(lib().gosh_draw_samples(ctx.h, lv.h, level, epoch, k, tag, _dev(out)))
+    return out
+
+
+def gosh_update_batch(ctx: Context, emb: torch.Tensor, src: torch.Tensor, samples: torch.Tensor, lr: float,
+                      level: int = 0, tag: int = 0, epoch: int = 0):
+    if samples.dim() != 2 or samples.shape[0] != src.numel():
+        raise ValueError("samples must be [nsrc, 1+k]")
+    k = samples.shape[1] - 1
+    ctx.check(lib().gosh_update_batch(ctx.h, _dev(emb, name="emb"), _dtype_code(emb), emb.shape[1], emb.shape[0],
+                                      src.numel(), _dev(src, torch.int32, "src"),
+                                      _dev(samples, torch.int32, "samples"), k, lr, level, tag, epoch))

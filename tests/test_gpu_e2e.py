@@ -1,0 +1,75 @@
+"""End-to-end Algorithm 2 on the GPU against the oracle: link-prediction AUC on
+the 20% held-out edges must agree within 0.01 (the GPU trains sources of an
+epoch concurrently, the oracle in order, so only the score is compared)."""
+import numpy as np
+import pytest
+import torch
+
+from synth import csr_from_pairs, evaluate_auc, init_rows, split_edges
+from tests.conftest import train_split
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_embed(gctx, sp, d, e, p, lr, k, threshold, dtype, orc):
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+
+    def init(n, dd):
+        f = init_rows(n, dd, 3)
+        if dtype == torch.bfloat16:
+            bits = orc.f32_to_bf16_rne(f).reshape(n, dd)
+            return torch.from_numpy(bits.view(np.int16).copy()).view(torch.bfloat16).cuda()
+        return torch.from_numpy(f).cuda()
+
+    cfg = EmbedConfig(d=d, epochs=e, p=p, lr=lr, k=k, dtype=dtype, threshold=threshold)
+    res = embed(gctx, g, cfg, init)
+    torch.cuda.synchronize()
+    M = res.emb.float().cpu().numpy().astype(np.float64)
+    return M, res
+
+
+def _oracle_embed(orc, sp, d, e, p, lr, k, threshold, bf16):
+    M, info = orc.gosh_embed(sp.offsets, sp.indices, lambda n, dd: init_rows(n, dd, 3), d, e, p,
+                             float(np.float32(lr)), k, seed=4, threshold=threshold, bf16=bf16)
+    return (orc.bf16_to_f64(M) if bf16 else M), info
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_config1_auc_matches_oracle(gctx, orc, dtype):
+    # R-MAT scale 12, d=32, k=1, lr 0.045, 200 epochs, threshold 64
+    sp = train_split(12, 16)
+    bf = dtype == torch.bfloat16
+    print(f"[e2e config1] dtype={dtype}", flush=True)
+    Mg, res = _gpu_embed(gctx, sp, 32, 200, 0.3, 0.045, 1, 64, dtype, orc)
+    Mo, info = _oracle_embed(orc, sp, 32, 200, 0.3, 0.045, 1, 64, bf)
+    assert res.sizes == info["sizes"]
+    assert list(res.schedule) == list(info["schedule"])
+    assert int(res.updates.item()) == sum(info["updates"])
+    a_g = evaluate_auc(Mg, sp, seed=5)
+    a_o = evaluate_auc(Mo, sp, seed=5)
+    print(f"[e2e config1] AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
+    assert abs(a_g - a_o) < 0.01
+
+
+def _geometric(n=4000, radius=0.03, seed=0):
+    from scipy.spatial import cKDTree
+    pts = np.random.default_rng(seed).random((n, 2))
+    pairs = np.array(sorted(cKDTree(pts).query_pairs(radius)))
+    return csr_from_pairs(n, pairs[:, 0], pairs[:, 1])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_geometric_graph_auc_matches_oracle(gctx, orc, dtype):
+    off, idx = _geometric()
+    sp = split_edges(off, idx, 2)
+    bf = dtype == torch.bfloat16
+    print(f"[e2e geometric] dtype={dtype}", flush=True)
+    Mg, _ = _gpu_embed(gctx, sp, 64, 200, 0.3, 0.045, 3, 64, dtype, orc)
+    Mo, _ = _oracle_embed(orc, sp, 64, 200, 0.3, 0.045, 3, 64, bf)
+    a_g = evaluate_auc(Mg, sp, seed=5)
+    a_o = evaluate_auc(Mo, sp, seed=5)
+    print(f"[e2e geometric] AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
+    assert a_o > 0.85
+    assert abs(a_g - a_o) < 0.01
