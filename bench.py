@@ -1,0 +1,184 @@
+"""Throughput of the GOSH hot path on one MI355X.
+
+A step is one whole pass of the method over the resident input graph:
+MultiEdgeCollapse coarsening of every level, TrainInGPU on every level
+(coarsest first, with its share of the epochs) and copy prolongation between
+levels.  Workload (default): the link-prediction train graph of a seeded
+R-MAT scale-20 graph (edge factor 16, a,b,c,d = 0.57,0.19,0.19,0.05; 80/20
+split), d = 128, k = 3 negatives, 600 epochs over all levels (p = 0.3),
+lr = 0.045, coarsening threshold 100.  The headline run stores rows in BF16
+(stochastic rounding, FP32 arithmetic); the same workload with FP32 rows is
+timed beside it, and both final embeddings are scored by link-prediction
+AUC on the held-out 20%.
+
+value = executed UpdateEmbed calls (edge-samples) per second of step wall
+time.  roofline: the dominant kernel is the level-0 training epoch; its
+algorithmic bytes per source are 2*d*b*(2+k) + 2*o + 4 (source row read and
+written, 1+k sample rows read and written, two offsets and one index), and
+its launch duration comes from events around level-0 training inside the
+timed steps.  cpu_baseline: the FP64 oracle's sequential trainer on a
+bounded sample of the same level-0 graph, single-threaded on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (scale, edge factor, d, k, epochs, threshold)
+    "rmat20": (20, 16, 128, 3, 600, 100),
+    "rmat12": (12, 16, 32, 1, 200, 64),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-epochs", type=int, default=4)
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    from synth import evaluate_auc, init_rows, rmat_csr, split_edges
+
+    scale, ef, d, k, epochs, threshold = WORKLOADS[a.workload]
+    p, lr = 0.3, 0.045
+    seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4, "eval": 5}
+    t0 = time.time()
+    off, idx = rmat_csr(scale, ef, seeds["graph"])
+    sp = split_edges(off, idx, seeds["split"])
+    log(f"graph ready: |V_train|={sp.n} nnz={len(sp.indices)} ({time.time() - t0:.1f}s)")
+
+    ctx = G.Context(0, seed=seeds["philox"])
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    G.gosh_validate_csr(ctx, g, check_symmetry=True)
+
+    def run(dtype, steps, warmup):
+        cfg = EmbedConfig(d=d, epochs=epochs, p=p, lr=lr, k=k, dtype=dtype, threshold=threshold)
+        lv = G.gosh_coarsen(ctx, g, threshold)
+        n_c = lv.sizes()[-1]
+        f = init_rows(n_c, d, seeds["init"])
+        init_dev = torch.from_numpy(f).cuda().to(dtype)   # RNE to BF16, resident before timing
+        del lv
+
+        def init_fn(n, dd):
+            assert n == n_c
+            return init_dev.clone()
+
+        for _ in range(warmup):
+            embed(ctx, g, cfg, init_fn)
+        torch.cuda.synchronize()
+        results = []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            results.append(embed(ctx, g, cfg, init_fn, level_events=True))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        updates = sum(int(r.updates.item()) for r in results)
+        last = results[-1]
+        lvl0 = [r.timings["train_events"][0] for r in results]
+        l0_ms = float(np.mean([s.elapsed_time(e) for s, e in lvl0]))
+        train_ms = float(np.mean([sum(s.elapsed_time(e) for s, e in r.timings["train_events"].values())
+                                  for r in results]))
+        return {
+            "wall_s": wall, "ms_per_step": 1e3 * wall / steps, "updates_per_step": updates // steps,
+            "value": updates / wall, "sizes": last.sizes, "schedule": last.schedule,
+            "level0_ms": l0_ms, "train_ms": train_ms, "emb": last.emb,
+        }
+
+    bf = run(torch.bfloat16, a.steps, a.warmup)
+    log(f"bf16: {bf['ms_per_step']:.2f} ms/step, {bf['value'] / 1e9:.3f} G edge-samples/s, "
+        f"level0 {bf['level0_ms']:.2f} ms, levels {bf['sizes']}")
+    f32 = None
+    if not a.no_fp32:
+        f32 = run(torch.float32, max(2, a.steps // 2), 1)
+        log(f"fp32: {f32['ms_per_step']:.2f} ms/step, {f32['value'] / 1e9:.3f} G edge-samples/s")
+
+    # roofline of the dominant kernel: the level-0 epoch launch
+    n0 = bf["sizes"][0]
+    e0 = bf["schedule"][0]
+    o = 4   # int32 offsets
+
+    def roof(r, b):
+        per_src = 2 * d * b * (2 + k) + 2 * o + 4
+        bytes_launch = n0 * per_src
+        launch_s = r["level0_ms"] / 1e3 / e0
+        ach = bytes_launch / launch_s / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_train level 0", "bytes_per_launch": bytes_launch,
+                "launch_us": round(launch_s * 1e6, 2)}
+
+    out = {
+        "metric": "edge-samples/s (executed UpdateEmbed calls) of the whole hot path at d=128",
+        "value": round(bf["value"], 1),
+        "unit": "edge-samples/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(bf["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {scale} ef {ef} link-prediction train graph "
+                               f"(|V|={n0}, nnz={len(sp.indices)}), d={d}, k={k}, e={epochs}, p={p}, "
+                               f"lr={lr}, threshold={threshold}, BF16 rows + SR",
+                   "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
+                   "updates_per_step": bf["updates_per_step"]},
+        "roofline": roof(bf, 2),
+        "train_ms_per_step": round(bf["train_ms"], 3),
+    }
+    if f32 is not None:
+        out["fp32"] = {"value": round(f32["value"], 1), "ms_per_step": round(f32["ms_per_step"], 3),
+                       "train_ms_per_step": round(f32["train_ms"], 3), "roofline": roof(f32, 4)}
+    if not a.no_auc:
+        t = time.time()
+        out["auc"] = {"bf16": round(evaluate_auc(bf["emb"].float().cpu().numpy(), sp, seeds["eval"],
+                                                 max_train=200_000), 4)}
+        if f32 is not None:
+            out["auc"]["fp32"] = round(evaluate_auc(f32["emb"].cpu().numpy(), sp, seeds["eval"],
+                                                    max_train=200_000), 4)
+        log(f"auc {out['auc']} ({time.time() - t:.1f}s)")
+    if not a.no_cpu_baseline:
+        import oracle
+        M = init_rows(n0, d, seeds["init"]).astype(np.float64)
+        oracle.train(sp.offsets, sp.indices, M, 1, lr, k, seeds["philox"], level=0)  # page in
+        t = time.perf_counter()
+        upd = oracle.train(sp.offsets, sp.indices, M, a.cpu_sample_epochs, lr, k, seeds["philox"], level=0)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(upd / dt, 1), "unit": "edge-samples/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"FP64 sequential TrainInGPU, {a.cpu_sample_epochs} epochs over the "
+                                         f"level-0 graph ({n0} sources, {upd} updates, {dt:.1f} s)"}
+        log(f"cpu baseline {upd / dt / 1e6:.2f} M edge-samples/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

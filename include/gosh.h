@@ -27,7 +27,9 @@
  *    the context seed, with counter (src, epoch, level | tag << 8,
  *    kind << 24 | slot << 16 | block): kind 0 draws the samples of a source,
  *    kind 1 gives stochastic-rounding bits (slot t = update t of the visit,
- *    slot 255 = the source row's write-back, block = element / 8).
+ *    slot 255 = the source row's write-back; element e of a d-wide row is in
+ *    32-bit word w = e/2, which draws block w mod (d/8) and uses its 16-bit
+ *    half 2*(w div (d/8)) + e mod 2, low half of each output word first).
  */
 #ifndef GOSH_H
 #define GOSH_H
@@ -65,14 +67,16 @@ typedef struct {
 /* ---------------------------------------------------------------- context */
 
 /* Creates a context on HIP device `device`.  `seed` keys every Philox
- * stream.  `hip_stream` is a hipStream_t to order work on (NULL: the
- * context creates its own).  `mem_cap_bytes` caps the device memory the
+ * stream.  `hip_stream` is the hipStream_t to order work on (NULL: the
+ * device's null stream).  `mem_cap_bytes` caps the device memory the
  * library allocates for this context (0 = no cap); allocations beyond it
  * fail with GOSH_E_CAP_EXCEEDED.  On success *out owns the context. */
 gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream,
                             uint64_t mem_cap_bytes, gosh_ctx** out);
+/* Frees the context and all device memory it allocated, including that of
+ * level hierarchies still alive; those can then only be destroyed. */
 gosh_status gosh_ctx_destroy(gosh_ctx* ctx);
-/* Orders subsequent work on `hip_stream` (NULL: the context's own stream). */
+/* Orders subsequent work on `hip_stream` (NULL: the null stream). */
 gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream);
 /* Blocks until all work enqueued by the context has finished. */
 gosh_status gosh_sync(gosh_ctx* ctx);
@@ -141,9 +145,12 @@ gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
  * score = (b - sigmoid(x)) * lr', M[src] += score M[u], then
  * M[u] += score M[src] with the updated source row.
  * `emb` is a caller-owned device array [n_level, d] of `dt`, updated in
- * place.  BF16 rows are widened to FP32 for the arithmetic and every
- * written row is stochastically rounded back (sample rows once per update,
- * the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
+ * place.  Sources of an epoch run concurrently; every row change is applied
+ * atomically (FP32: atomic add per element; BF16: the exact difference to the
+ * rounded value, added per 2-element word), so concurrent updates of a shared
+ * row are all kept.  BF16 rows are widened to FP32 for
+ * the arithmetic and every written row is stochastically rounded back
+ * (sample rows once per update, the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
  * lr finite and >= 0.  `tag` (24 bits) separates independent random
  * streams.  If `updates_dev` is not NULL, the number of UpdateEmbed calls
  * executed is added to *updates_dev (device uint64).  Asynchronous. */

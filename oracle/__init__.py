@@ -44,7 +44,7 @@ def lib():
         L.orc_draw_samples.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32,
                                        C.c_int32, C.c_int64, C.c_int32, _i32p]
         L.orc_sr_bits.argtypes = [C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int64,
-                                  C.c_uint32, C.c_int32]
+                                  C.c_uint32, C.c_int32, C.c_int32]
         L.orc_sr_bits.restype = C.c_uint32
         L.orc_bf16_sr.argtypes = [C.c_float, C.c_uint32]
         L.orc_bf16_sr.restype = C.c_uint16
@@ -109,8 +109,8 @@ def draw_all(offsets, indices, seed, level, tag, epoch, k) -> np.ndarray:
     return out
 
 
-def sr_bits(seed, level, tag, epoch, src, slot, e) -> int:
-    return int(lib().orc_sr_bits(seed, level, tag, epoch, src, slot, e))
+def sr_bits(seed, level, tag, epoch, src, slot, e, d) -> int:
+    return int(lib().orc_sr_bits(seed, level, tag, epoch, src, slot, e, d))
 
 
 def bf16_sr(x: float, r16: int) -> int:

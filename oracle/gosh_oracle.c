@@ -91,12 +91,18 @@ void orc_draw_samples(const int64_t* offsets, const int32_t* indices, int64_t n,
 }
 
 uint32_t orc_sr_bits(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
-                     int64_t src, uint32_t slot, int32_t e)
+                     int64_t src, uint32_t slot, int32_t e, int32_t d)
 {
-    uint32_t w[4];
-    orc_stream_block(seed, level, tag, epoch, src, 1u, slot, (uint32_t)(e / 8), w);
-    int32_t h = e % 8;
-    uint32_t word = w[h / 2];
+    /* Element e lies in 32-bit word w = e / 2 of the row.  With L = d / 8,
+     * word w draws from block w mod L, and inside that block's 8 halves it
+     * takes half 2 * (w div L) + (e mod 2) (low half of a 32-bit output
+     * word first). */
+    const int32_t L = d >= 8 ? d / 8 : 1;
+    const int32_t w = e / 2;
+    uint32_t out[4];
+    orc_stream_block(seed, level, tag, epoch, src, 1u, slot, (uint32_t)(w % L), out);
+    const int32_t h = 2 * (w / L) + (e % 2);
+    const uint32_t word = out[h / 2];
     return (h & 1) ? (word >> 16) : (word & 0xFFFFu);
 }
 
@@ -197,7 +203,7 @@ int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
         for (int32_t e = 0; e < d; ++e) {
             double val = m[e] + s[e] * score;
             if (M->bf16) {
-                uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, (uint32_t)t, e);
+                uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, (uint32_t)t, e, d);
                 ((uint16_t*)M->rows)[u * d + e] = orc_bf16_sr((float)val, r);
             } else {
                 ((double*)M->rows)[u * d + e] = val;
@@ -207,7 +213,7 @@ int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
     }
     for (int32_t e = 0; e < d; ++e) {
         if (M->bf16) {
-            uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, 0xFFu, e);
+            uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, 0xFFu, e, d);
             ((uint16_t*)M->rows)[src * d + e] = orc_bf16_sr((float)s[e], r);
         } else {
             ((double*)M->rows)[src * d + e] = s[e];

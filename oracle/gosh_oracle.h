@@ -41,9 +41,11 @@ void orc_draw_samples(const int64_t* offsets, const int32_t* indices, int64_t n,
                       uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
                       int64_t src, int32_t k, int32_t* out);
 
-/* 16 stochastic-rounding bits for element e of update slot `slot`. */
+/* 16 stochastic-rounding bits for element e (row dimension d) of update
+ * slot `slot`: element e sits in 32-bit word w = e/2; with L = d/8 the word
+ * draws from block w mod L and takes half 2*(w div L) + e mod 2. */
 uint32_t orc_sr_bits(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
-                     int64_t src, uint32_t slot, int32_t e);
+                     int64_t src, uint32_t slot, int32_t e, int32_t d);
 
 /* FP32 -> BF16 with stochastic rounding by 16 random bits. */
 uint16_t orc_bf16_sr(float x, uint32_t r16);

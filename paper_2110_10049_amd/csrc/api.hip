@@ -104,6 +104,7 @@ void set_device(Ctx* c) { GOSH_HIP(hipSetDevice(c->device)); }
 
 const gosh::Level& level_of(const gosh_levels* lv, int32_t i) {
     GOSH_REQUIRE(lv, GOSH_E_INVALID_ARG, "null levels");
+    GOSH_REQUIRE(lv->ctx, GOSH_E_INVALID_ARG, "levels outlived their context");
     GOSH_REQUIRE(i >= 0 && i < static_cast<int32_t>(lv->lv.size()), GOSH_E_INVALID_ARG,
                  "level out of range");
     return lv->lv[i];
@@ -142,12 +143,7 @@ gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream, uint64_
         c->seed = seed;
         c->cap = mem_cap_bytes;
         set_device(c);
-        if (hip_stream) {
-            c->stream = static_cast<hipStream_t>(hip_stream);
-        } else {
-            GOSH_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
-            c->stream = c->own_stream;
-        }
+        c->stream = static_cast<hipStream_t>(hip_stream);
         c->scratch = c->alloc(4096);
         GOSH_HIP(hipMemsetAsync(c->scratch, 0, 4096, c->stream));
     });
@@ -163,28 +159,22 @@ gosh_status gosh_ctx_destroy(gosh_ctx* ctx) {
     if (!ctx) return GOSH_OK;
     Ctx* c = &ctx->c;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    // hierarchies that outlive the context lose their storage with it
+    for (gosh_levels* lv : ctx->levels) {
+        lv->owner = nullptr;
+        lv->ctx = nullptr;
+    }
     for (auto& kv : c->live) (void)hipFree(kv.first);
     for (auto& kv : c->cache) (void)hipFree(kv.second);
-    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete ctx;
     return GOSH_OK;
 }
 
 gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream) {
     if (!ctx) return GOSH_E_INVALID_ARG;
-    return guarded(ctx, [&] {
-        Ctx* c = &ctx->c;
-        if (hip_stream) {
-            c->stream = static_cast<hipStream_t>(hip_stream);
-        } else {
-            if (!c->own_stream) {
-                set_device(c);
-                GOSH_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
-            }
-            c->stream = c->own_stream;
-        }
-    });
+    ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+    return GOSH_OK;
 }
 
 gosh_status gosh_sync(gosh_ctx* ctx) {
@@ -234,7 +224,9 @@ gosh_status gosh_coarsen(gosh_ctx* ctx, const gosh_csr* g0, int64_t threshold, d
         set_device(&ctx->c);
         gosh::validate_csr(&ctx->c, g0, false);
         lv = new gosh_levels();
+        lv->owner = ctx;
         lv->ctx = &ctx->c;
+        ctx->levels.insert(lv);
         gosh::coarsen(&ctx->c, g0, threshold, max_ratio, lv);
         GOSH_HIP(hipStreamSynchronize(ctx->c.stream));
     });
@@ -255,7 +247,9 @@ gosh_status gosh_levels_single(gosh_ctx* ctx, const gosh_csr* g0, gosh_levels** 
         set_device(&ctx->c);
         gosh::validate_csr(&ctx->c, g0, false);
         lv = new gosh_levels();
+        lv->owner = ctx;
         lv->ctx = &ctx->c;
+        ctx->levels.insert(lv);
         gosh::Level L;
         L.n = g0->n;
         L.nnz = g0->nnz;
@@ -279,6 +273,7 @@ gosh_status gosh_levels_destroy(gosh_levels* lv) {
         (void)hipSetDevice(lv->ctx->device);
         for (auto& L : lv->lv) gosh::free_level(lv->ctx, L);
     }
+    if (lv->owner) lv->owner->levels.erase(lv);
     delete lv;
     return GOSH_OK;
 }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -36,8 +37,7 @@ struct Error : std::runtime_error {
 struct Ctx {
     int device = 0;
     uint64_t seed = 0;
-    hipStream_t stream = nullptr;
-    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;   // nullptr = the device's null stream
     uint64_t cap = 0;          // 0 = unlimited
     uint64_t in_use = 0;       // bytes held by live allocations and the cache
     bool deterministic = false;
@@ -95,11 +95,15 @@ struct Level {
 
 }  // namespace gosh
 
+struct gosh_levels;
+
 struct gosh_ctx {
     gosh::Ctx c;
+    std::set<gosh_levels*> levels;   // live hierarchies built on this context
 };
 
 struct gosh_levels {
+    gosh_ctx* owner = nullptr;       // cleared when the context is destroyed first
     gosh::Ctx* ctx = nullptr;
     std::vector<gosh::Level> lv;
 };

@@ -1,24 +1,27 @@
 // TrainInGPU (Algorithm 3, Section 3.1) with UpdateEmbed (Algorithm 1) for
 // gfx950.
 //
-// Layout: every lane owns 8 consecutive elements of a row (32 B of FP32 or
-// 16 B of BF16, one or two dwordx4 accesses), so a source with dimension d
-// is served by a group of d/8 lanes and one wave64 carries 64/(d/8) sources
-// (d=128: 4 sources per wave, d=32: 16).  The dot product is reduced inside
+// Layout: every lane owns 8 elements of a row, so a source with dimension d
+// is served by a group of L = d/8 lanes and one wave64 carries 64/L sources
+// (d=128: 4 sources per wave, d=32: 16); the elements are interleaved across
+// the group (see RowIO) so that each memory instruction covers contiguous
+// bytes.  The dot product is reduced inside
 // the group with DPP (no LDS round trip).  Each group draws its samples from
 // Philox, issues the loads of the source row and of all 1+k sample rows at
-// once, then runs the dependent chain of updates from registers and writes
-// every row back; the source row plays the role of the paper's
-// shared-memory staged row (Section 3.1), here kept in registers.  A sample
-// that repeats within one source is forwarded from the earlier update's
-// registers, so the chain has the sequential semantics of Algorithm 3.
-// Sources of one epoch run concurrently without locks; an epoch is one
-// launch, so epochs never overlap (Section 3.1).
+// once, then runs the dependent chain of updates from registers; the source
+// row plays the role of the paper's shared-memory staged row (Section 3.1),
+// here kept in registers.  A sample that repeats within one source is
+// forwarded from the earlier update's registers, so the chain has the
+// sequential semantics of Algorithm 3.  Sources of one epoch run
+// concurrently without locks; an epoch is one launch, so epochs never
+// overlap (Section 3.1).  Each sample row's change and, at the end, the
+// source row's change are applied atomically to memory (see RowIO).
 //
 // BF16 storage: rows are widened to FP32, all arithmetic is FP32, and each
 // written row is stochastically rounded with Philox bits (kind 1, slot =
-// update index or 255 for the source write-back, block = element / 8): the
-// lane that owns elements 8j..8j+7 draws exactly block j.
+// update index or 255 for the source write-back): element e lies in 32-bit
+// word w = e/2, which draws block w mod L and takes half 2*(w div L) + e mod 2,
+// so lane gl draws exactly one block (block gl) per row update.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -51,50 +54,80 @@ struct TrainParams {
 
 enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2 };
 
+// Row access.  A lane of the group of L = d/8 lanes owns row elements
+// gl + L*i (FP32) or 32-bit words gl + L*i (BF16, two elements each), so
+// every load and every atomic instruction of a group covers one contiguous
+// run of the row.
+//
+// Writes are atomic: sources of an epoch run concurrently and share rows, and
+// a plain read-modify-write store would drop every concurrent update but the
+// last one -- on small levels, where a whole epoch is in flight at once,
+// nearly all of them.  FP32 rows receive their changes with atomic adds.
+// BF16 rows receive, per 32-bit word, the exact difference between the
+// stochastically rounded new value and the value this visit started from,
+// through the packed BF16 atomic add: uncontended, the stored row becomes
+// exactly the rounded value; contended, the concurrent changes add up.
 template <bool BF16>
 struct RowIO;
 
 template <>
 struct RowIO<false> {
     using Elem = float;
-    __device__ static void load(const float* M, int64_t row, int D, int gl, float (&x)[kEPL]) {
-        const float4* p = reinterpret_cast<const float4*>(M + row * D + gl * kEPL);
-        const float4 a = p[0], b = p[1];
-        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    template <int L>
+    __device__ static void load(const float* M, int64_t row, int gl, float (&x)[kEPL]) {
+        const float* p = M + row * (L * kEPL) + gl;
+#pragma unroll
+        for (int i = 0; i < kEPL; ++i) x[i] = p[L * i];
     }
-    __device__ static void store(float* M, int64_t row, int D, int gl, float (&x)[kEPL], uint4) {
-        float4* p = reinterpret_cast<float4*>(M + row * D + gl * kEPL);
-        p[0] = make_float4(x[0], x[1], x[2], x[3]);
-        p[1] = make_float4(x[4], x[5], x[6], x[7]);
+    template <int L>
+    __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[kEPL]) {
+        float* p = M + row * (L * kEPL) + gl;
+#pragma unroll
+        for (int i = 0; i < kEPL; ++i)
+            __hip_atomic_fetch_add(p + L * i, dx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
+
+typedef __bf16 __attribute__((ext_vector_type(2))) bf16x2_t;
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
 
 template <>
 struct RowIO<true> {
     using Elem = uint16_t;
-    __device__ static void load(const uint16_t* M, int64_t row, int D, int gl, float (&x)[kEPL]) {
-        const uint4 w = *reinterpret_cast<const uint4*>(M + row * D + gl * kEPL);
-        x[0] = bf16_lo(w.x); x[1] = bf16_hi(w.x);
-        x[2] = bf16_lo(w.y); x[3] = bf16_hi(w.y);
-        x[4] = bf16_lo(w.z); x[5] = bf16_hi(w.z);
-        x[6] = bf16_lo(w.w); x[7] = bf16_hi(w.w);
-    }
-    // Rounds x to BF16 with the 8 random halves of `r`, stores it and leaves
-    // the rounded values in x.
-    __device__ static void store(uint16_t* M, int64_t row, int D, int gl, float (&x)[kEPL], uint4 r) {
-        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-        uint32_t packed[4];
+    template <int L>
+    __device__ static void load(const uint16_t* M, int64_t row, int gl, float (&x)[kEPL]) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * (L * kEPL)) + gl;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t lo = bf16_sr(x[2 * i], rw[i] & 0xFFFFu);
-            const uint32_t hi = bf16_sr(x[2 * i + 1], rw[i] >> 16);
-            packed[i] = lo | (hi << 16);
-            x[2 * i] = __uint_as_float(lo << 16);
-            x[2 * i + 1] = __uint_as_float(hi << 16);
+        for (int i = 0; i < kEPL / 2; ++i) {
+            const uint32_t w = p[L * i];
+            x[2 * i] = bf16_lo(w);
+            x[2 * i + 1] = bf16_hi(w);
         }
-        *reinterpret_cast<uint4*>(M + row * D + gl * kEPL) =
-            make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    }
+    // cur: the values this visit last saw (exact BF16), v: the FP32 results.
+    // Element h of the lane uses random half h of r.  out: the rounded values.
+    template <int L>
+    __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[kEPL],
+                                  const float (&v)[kEPL], uint4 r, float (&out)[kEPL]) {
+        uint32_t* p = reinterpret_cast<uint32_t*>(M + row * (L * kEPL)) + gl;
+        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < kEPL / 2; ++i) {
+            const uint32_t t0 = bf16_sr(v[2 * i], rw[i] & 0xFFFFu);
+            const uint32_t t1 = bf16_sr(v[2 * i + 1], rw[i] >> 16);
+            out[2 * i] = __uint_as_float(t0 << 16);
+            out[2 * i + 1] = __uint_as_float(t1 << 16);
+            const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
+                               (bf16_rne_bits(out[2 * i + 1] - cur[2 * i + 1]) << 16);
+            if (d != 0u)
+                __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                    (__attribute__((address_space(1))) bf16x2_t*)(p + L * i),
+                    __builtin_bit_cast(bf16x2_t, d));
+        }
     }
 };
 
@@ -161,11 +194,11 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
 
     float s[kEPL];
     float m[KMAX + 1][kEPL];
-    IO::load(M, src, D, gl, s);
+    IO::template load<L>(M, src, gl, s);
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) {
         if (u[t] >= 0 && u[t] != src) {
-            IO::load(M, u[t], D, gl, m[t]);
+            IO::template load<L>(M, u[t], gl, m[t]);
         } else {
 #pragma unroll
             for (int e = 0; e < kEPL; ++e) m[t][e] = 0.0f;
@@ -174,6 +207,9 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
 
     int done = 0;
     const float lr = P.lr;
+    float s0[kEPL];
+#pragma unroll
+    for (int e = 0; e < kEPL; ++e) s0[e] = s[e];
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) {
         if (t > k) break;
@@ -198,23 +234,41 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
         const float g = (b - sigmoidf_(x)) * lr;
 #pragma unroll
         for (int e = 0; e < kEPL; ++e) s[e] = fmaf(g, m[t][e], s[e]);
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
+                                                   stream_word3(1, static_cast<uint32_t>(t),
+                                                                static_cast<uint32_t>(gl))),
+                                        P.key0, P.key1);
+            float v[kEPL], out[kEPL];
 #pragma unroll
-        for (int e = 0; e < kEPL; ++e) m[t][e] = fmaf(g, s[e], m[t][e]);
-        uint4 bits = make_uint4(0, 0, 0, 0);
-        if constexpr (BF16)
-            bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
-                                       stream_word3(1, static_cast<uint32_t>(t), static_cast<uint32_t>(gl))),
-                            P.key0, P.key1);
-        IO::store(M, ut, D, gl, m[t], bits);
+            for (int e = 0; e < kEPL; ++e) v[e] = fmaf(g, s[e], m[t][e]);
+            IO::template commit<L>(M, ut, gl, m[t], v, bits, out);
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) m[t][e] = out[e];
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) {
+                dx[e] = g * s[e];
+                m[t][e] += dx[e];
+            }
+            IO::template add<L>(M, ut, gl, dx);
+        }
         ++done;
     }
     if (done) {
-        uint4 bits = make_uint4(0, 0, 0, 0);
-        if constexpr (BF16)
-            bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
-                                       stream_word3(1, 0xFFu, static_cast<uint32_t>(gl))),
-                            P.key0, P.key1);
-        IO::store(M, src, D, gl, s, bits);
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
+                                                   stream_word3(1, 0xFFu, static_cast<uint32_t>(gl))),
+                                        P.key0, P.key1);
+            float out[kEPL];
+            IO::template commit<L>(M, src, gl, s0, s, bits, out);
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) dx[e] = s[e] - s0[e];
+            IO::template add<L>(M, src, gl, dx);
+        }
     }
 }
 

@@ -37,8 +37,11 @@ class EmbedResult:
 
 
 def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels | None = None,
-          coarsen: bool = True) -> EmbedResult:
-    """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level."""
+          coarsen: bool = True, level_events: bool = False) -> EmbedResult:
+    """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level.
+
+    With level_events, timings["train_events"][i] holds a (start, end) pair
+    of events recorded on the context stream around level i's training."""
     if levels is None:
         levels = G.gosh_coarsen(ctx, g0, cfg.threshold, cfg.max_ratio) if coarsen else G.gosh_levels_single(ctx, g0)
     D = levels.count()
@@ -49,10 +52,18 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
     if M.dtype != cfg.dtype or tuple(M.shape) != (sizes[-1], cfg.d):
         raise ValueError("init_fn returned a wrong shape or dtype")
     counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    events = {}
     for i in range(D - 1, -1, -1):
+        if level_events:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record(ctx.stream)
         G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
+        if level_events:
+            ev[1].record(ctx.stream)
+            events[i] = ev
         if i > 0:
             fine = torch.empty((sizes[i - 1], cfg.d), dtype=cfg.dtype, device=dev)
             G.gosh_prolong(ctx, levels, i - 1, M, fine)
             M = fine
-    return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels)
+    return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels,
+                       timings={"train_events": events})

@@ -92,10 +92,18 @@ def test_positive_uniform_over_neighbours(orc):
 
 
 def test_sr_bits_layout(orc):
-    # element e takes the (e mod 8)-th 16-bit half of block e // 8 (low half first)
-    w = orc.stream_block(5, 1, 0, 2, 9, 1, 3, 4)
-    for h in range(8):
-        e = 32 + h
-        word = int(w[h // 2])
-        want = (word >> 16) if h & 1 else (word & 0xFFFF)
-        assert orc.sr_bits(5, 1, 0, 2, 9, 3, e) == want
+    # element e sits in 32-bit word w = e // 2; with L = d // 8 the word draws
+    # from block w % L and takes half 2 * (w // L) + e % 2 (low half first)
+    for d in (8, 32, 128, 256):
+        L = d // 8
+        for e in range(d):
+            w = e // 2
+            blk = orc.stream_block(5, 1, 0, 2, 9, 1, 3, w % L)
+            h = 2 * (w // L) + e % 2
+            word = int(blk[h // 2])
+            want = (word >> 16) if h & 1 else (word & 0xFFFF)
+            assert orc.sr_bits(5, 1, 0, 2, 9, 3, e, d) == want
+    # every (block, half) pair of the d/8 blocks is used exactly once per row
+    d = 64
+    seen = {(((e // 2) % 8), 2 * ((e // 2) // 8) + e % 2) for e in range(d)}
+    assert len(seen) == d

@@ -182,8 +182,8 @@ def test_rne_matches_numpy_cast(orc):
 
 
 def test_bf16_visit_uses_sr_bits(orc):
-    # Sample-row element e of slot t is SR-rounded with bits (kind 1, slot t,
-    # block e // 8); the source row with slot 0xFF at write-back.
+    # Sample-row element e of slot t is SR-rounded with the bits of (kind 1,
+    # slot t, element e); the source row with slot 0xFF at write-back.
     rng = np.random.default_rng(11)
     d = 16
     f = rng.normal(size=(3, d)).astype(np.float32) * 0.3
@@ -197,8 +197,8 @@ def test_bf16_visit_uses_sr_bits(orc):
     m1 = m + g * s1
     orc.visit(M, 0, [1], lr, seed, level, tag, ep)
     for e in range(d):
-        assert M[1, e] == orc.bf16_sr(float(np.float32(m1[e])), orc.sr_bits(seed, level, tag, ep, 0, 0, e))
-        assert M[0, e] == orc.bf16_sr(float(np.float32(s1[e])), orc.sr_bits(seed, level, tag, ep, 0, 0xFF, e))
+        assert M[1, e] == orc.bf16_sr(float(np.float32(m1[e])), orc.sr_bits(seed, level, tag, ep, 0, 0, e, d))
+        assert M[0, e] == orc.bf16_sr(float(np.float32(s1[e])), orc.sr_bits(seed, level, tag, ep, 0, 0xFF, e, d))
 
 
 def test_train_lr_schedule_and_determinism(orc):
