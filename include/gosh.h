@@ -117,15 +117,17 @@ gosh_status gosh_level_shape(const gosh_levels* lv, int32_t level, int64_t* n, i
 /* Device view of level `level` (valid while lv lives). */
 gosh_status gosh_level_csr(const gosh_levels* lv, int32_t level, gosh_csr* out);
 /* Device pointer to map_level (|V_level| int32 entries, values in
- * [0, |V_{level+1}|)) and to the cluster sizes of level+1. */
+ * [0, |V_{level+1}|)) and to the sizes of level+1's clusters (|V_{level+1}|
+ * int32; computed on the context stream at the first request). */
 gosh_status gosh_level_map(const gosh_levels* lv, int32_t level, const int32_t** map_dev,
                            const int32_t** clsz_dev);
-/* Copies a level to host memory; any of the three pointers may be NULL.
+/* Copies a level to host memory; any of the pointers may be NULL.
  * offsets_host receives n+1 int64 values whatever the device width;
- * map_host receives map_level (invalid for the coarsest level). Synchronous. */
+ * map_host receives map_level and clsz_host the |V_{level+1}| cluster sizes
+ * (both invalid for the coarsest level).  Synchronous. */
 gosh_status gosh_level_copy_out(gosh_ctx* ctx, const gosh_levels* lv, int32_t level,
                                 int64_t* offsets_host, int32_t* indices_host,
-                                int32_t* map_host);
+                                int32_t* map_host, int32_t* clsz_host);
 
 /* ---------------------------------------------------------------- training */
 
@@ -146,9 +148,9 @@ gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
  * M[u] += score M[src] with the updated source row.
  * `emb` is a caller-owned device array [n_level, d] of `dt`, updated in
  * place.  Sources of an epoch run concurrently; every row change is applied
- * atomically (FP32: atomic add per element; BF16: the exact difference to the
- * rounded value, added per 2-element word), so concurrent updates of a shared
- * row are all kept.  BF16 rows are widened to FP32 for
+ * with atomic adds (FP32: per element; BF16: the exact difference to the
+ * rounded value, per 2-element word), so concurrent updates of a shared row
+ * are all kept.  BF16 rows are widened to FP32 for
  * the arithmetic and every written row is stochastically rounded back
  * (sample rows once per update, the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
  * lr finite and >= 0.  `tag` (24 bits) separates independent random

@@ -256,7 +256,6 @@ gosh_status gosh_levels_single(gosh_ctx* ctx, const gosh_csr* g0, gosh_levels** 
         L.off64 = g0->offsets_is_i64 != 0;
         L.offsets = g0->offsets;
         L.indices = g0->indices;
-        L.n_deg0 = gosh::count_isolated(&ctx->c, L);
         lv->lv.push_back(L);
     });
     if (st != GOSH_OK) {
@@ -304,14 +303,23 @@ gosh_status gosh_level_csr(const gosh_levels* lv, int32_t level, gosh_csr* out) 
 
 gosh_status gosh_level_map(const gosh_levels* lv, int32_t level, const int32_t** map_dev,
                            const int32_t** clsz_dev) {
-    if (!lv || level < 0 || level + 1 >= static_cast<int32_t>(lv->lv.size())) return GOSH_E_INVALID_ARG;
+    if (!lv || !lv->ctx || level < 0 || level + 1 >= static_cast<int32_t>(lv->lv.size())) return GOSH_E_INVALID_ARG;
     if (map_dev) *map_dev = lv->lv[level].map;
-    if (clsz_dev) *clsz_dev = lv->lv[level].clsz;
+    if (clsz_dev) {
+        gosh::Ctx* c = lv->ctx;
+        try {
+            GOSH_HIP(hipSetDevice(c->device));
+            *clsz_dev = gosh::cluster_sizes(c, lv->lv[level], lv->lv[level + 1].n);
+        } catch (const gosh::Error& e) {
+            c->err = e.what();
+            return e.code;
+        }
+    }
     return GOSH_OK;
 }
 
 gosh_status gosh_level_copy_out(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, int64_t* offsets_host,
-                                int32_t* indices_host, int32_t* map_host) {
+                                int32_t* indices_host, int32_t* map_host, int32_t* clsz_host) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     return guarded(ctx, [&] {
         const gosh::Level& L = level_of(lv, level);
@@ -333,6 +341,13 @@ gosh_status gosh_level_copy_out(gosh_ctx* ctx, const gosh_levels* lv, int32_t le
             GOSH_REQUIRE(L.map, GOSH_E_INVALID_ARG, "the coarsest level has no map");
             if (L.n > 0)
                 GOSH_HIP(hipMemcpyAsync(map_host, L.map, 4 * L.n, hipMemcpyDeviceToHost, c->stream));
+        }
+        if (clsz_host) {
+            GOSH_REQUIRE(L.map, GOSH_E_INVALID_ARG, "the coarsest level has no clusters");
+            const int64_t nn = lv->lv[level + 1].n;
+            const int32_t* cs = gosh::cluster_sizes(c, L, nn);
+            if (nn > 0)
+                GOSH_HIP(hipMemcpyAsync(clsz_host, cs, 4 * nn, hipMemcpyDeviceToHost, c->stream));
         }
         GOSH_HIP(hipStreamSynchronize(c->stream));
     });

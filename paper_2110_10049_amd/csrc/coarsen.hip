@@ -62,7 +62,9 @@ __global__ void k_degree(const Off* off, int64_t n, int64_t nnz, uint8_t* light,
     }
 }
 
-__global__ void k_sort_keys(const int64_t* deg, int64_t n, uint64_t maxdeg, uint32_t* key, uint32_t* val) {
+__global__ void k_sort_keys(const int64_t* deg, int64_t n, const unsigned long long* maxdeg_dev, uint32_t* key,
+                            uint32_t* val) {
+    const uint64_t maxdeg = *maxdeg_dev;
     GRID_STRIDE(v, n) {
         key[v] = static_cast<uint32_t>(maxdeg - static_cast<uint64_t>(deg[v]));
         val[v] = static_cast<uint32_t>(v);
@@ -94,66 +96,81 @@ __global__ void k_flag_lower(const int32_t* src, const int32_t* idx, int64_t nnz
     }
 }
 
-__global__ void k_write_lower(const int32_t* src, const int32_t* idx, int64_t nnz, const int32_t* flag,
-                              const int64_t* pos, int2* low) {
+// The kept entries stay in CSR order, so vertex v's eligible earlier
+// neighbours form the segment [lstart[v], lstart[v+1]) of `lower`.
+__global__ void k_write_lower(const int32_t* idx, int64_t nnz, const int32_t* flag, const int64_t* pos,
+                              int32_t* lower) {
     GRID_STRIDE(p, nnz) {
-        if (flag[p]) low[pos[p]] = make_int2(src[p], idx[p]);
+        if (flag[p]) lower[pos[p]] = idx[p];
+    }
+}
+
+template <class Off>
+__global__ void k_lower_starts(const Off* off, int64_t n, int64_t nnz, const int32_t* flag, const int64_t* pos,
+                               int64_t* lstart) {
+    const int64_t m = nnz > 0 ? pos[nnz - 1] + flag[nnz - 1] : 0;
+    GRID_STRIDE(v, n + 1) {
+        const int64_t o = off[v];
+        lstart[v] = o < nnz ? pos[o] : m;
     }
 }
 
 // ---------------------------------------------------------------- hub selection rounds
-__global__ void k_round_edges(const int2* low, int64_t m, const uint8_t* state, uint8_t* saw_in,
-                              uint8_t* saw_pending) {
-    GRID_STRIDE(i, m) {
-        const int2 e = low[i];
-        if (state[e.x] != kUndecided) continue;
-        const uint8_t su = state[e.y];
-        if (su == kIn) saw_in[e.x] = 1;
-        else if (su == kUndecided) saw_pending[e.x] = 1;
-    }
-}
-
-__global__ void k_round_vertices(int64_t n, uint8_t* state, uint8_t* saw_in, uint8_t* saw_pending,
-                                 unsigned long long* undecided) {
+// In place: a decision only uses states that are final (IN, OUT), so reading
+// a neighbour before or after its own decision in the same round is safe.
+__global__ void k_round(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
+                        unsigned long long* undecided) {
     unsigned long long cnt = 0;
     GRID_STRIDE(v, n) {
-        if (state[v] == kUndecided) {
-            if (saw_in[v]) state[v] = kOut;
-            else if (!saw_pending[v]) state[v] = kIn;
-            else ++cnt;
-            saw_pending[v] = 0;
+        if (state[v] != kUndecided) continue;
+        bool any_in = false, pending = false;
+        for (int64_t i = lstart[v], e = lstart[v + 1]; i < e; ++i) {
+            const uint8_t su = state[lower[i]];
+            if (su == kIn) {
+                any_in = true;
+                break;
+            }
+            pending |= (su == kUndecided);
         }
+        if (any_in) state[v] = kOut;
+        else if (!pending) state[v] = kIn;
+        else ++cnt;
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(undecided, cnt);
-}
-
-// earliest hub among the eligible earlier neighbours of each marked vertex
-__global__ void k_best_hub(const int2* low, int64_t m, const uint8_t* state, const int32_t* rank,
-                           int32_t* best) {
-    GRID_STRIDE(i, m) {
-        const int2 e = low[i];
-        if (state[e.x] == kOut && state[e.y] == kIn) atomicMin(&best[e.x], rank[e.y]);
-    }
 }
 
 __global__ void k_hub_flags_by_rank(const uint32_t* perm, int64_t n, const uint8_t* state, int32_t* hf) {
     GRID_STRIDE(r, n) hf[r] = state[perm[r]] == kIn ? 1 : 0;
 }
 
-__global__ void k_assign(int64_t n, const uint8_t* state, const int32_t* rank, const int32_t* best,
-                         const int64_t* cid_by_rank, int32_t* map, int32_t* clsz, unsigned int* bad) {
+// A hub keeps its own cluster; a marked vertex joins the earliest hub among
+// its eligible earlier neighbours.  Cluster id = hubs before it in pi order.
+__global__ void k_assign(int64_t n, const int64_t* lstart, const int32_t* lower, const uint8_t* state,
+                         const int32_t* rank, const int64_t* cid_by_rank, int32_t* map, unsigned int* bad) {
     GRID_STRIDE(v, n) {
-        const int32_t r = state[v] == kIn ? rank[v] : best[v];
-        if (state[v] == kUndecided || r < 0 || r >= n) {   // cannot happen for a valid CSR
+        int32_t r = -1;
+        if (state[v] == kIn) {
+            r = rank[v];
+        } else if (state[v] == kOut) {
+            int32_t best = INT32_MAX;
+            for (int64_t i = lstart[v], e = lstart[v + 1]; i < e; ++i) {
+                const int32_t u = lower[i];
+                if (state[u] == kIn) best = min(best, rank[u]);
+            }
+            r = best;
+        }
+        if (r < 0 || r >= n) {   // cannot happen once every vertex is decided
             map[v] = 0;
             atomicOr(bad, 1u);
             continue;
         }
-        const int32_t c = static_cast<int32_t>(cid_by_rank[r]);
-        map[v] = c;
-        atomicAdd(&clsz[c], 1);
+        map[v] = static_cast<int32_t>(cid_by_rank[r]);
     }
+}
+
+__global__ void k_cluster_sizes(const int32_t* map, int64_t n, int32_t* clsz) {
+    GRID_STRIDE(v, n) atomicAdd(&clsz[map[v]], 1);
 }
 
 // ---------------------------------------------------------------- coarse graph
@@ -207,45 +224,54 @@ __global__ void k_offsets_lb(const K* ukeys, int64_t m, int64_t n_next, int bb, 
 }
 
 // ---------------------------------------------------------------- validation
-// Offsets must be non-decreasing before any kernel may read a row.
+// Offsets must start at 0, end at nnz and never decrease before any kernel
+// may read a row.
 template <class Off>
 __global__ void k_check_offsets(const Off* off, int64_t n, int64_t nnz, unsigned int* bad) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (static_cast<int64_t>(off[0]) != 0 || static_cast<int64_t>(off[n]) != nnz))
+        atomicOr(bad, 1u);
     GRID_STRIDE(v, n) {
         const int64_t b = off[v], e = off[v + 1];
         if (e < b || b < 0 || e > nnz) atomicOr(bad, 1u);
     }
 }
 
+// Entry checks once the rows are known to lie inside [0, nnz).
 template <class Off>
-__global__ void k_validate(const Off* off, const int32_t* idx, int64_t n, int check_sym,
-                           unsigned int* bad) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wpb = blockDim.x / 64;
-    for (int64_t v = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); v < n;
-         v += static_cast<int64_t>(gridDim.x) * wpb) {
-        const int64_t b = off[v], e = off[v + 1];
-        unsigned int f = 0;
-        if (e < b) f |= 1u;
-        for (int64_t p = b + lane; p < e; p += 64) {
-            const int32_t u = idx[p];
-            if (u < 0 || u >= n) { f |= 2u; continue; }
-            if (u == v) f |= 4u;
-            if (p > b && idx[p - 1] >= u) f |= 8u;
-            if (check_sym) {
-                int64_t lo = off[u], hi = off[u + 1];
-                bool found = false;
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    const int32_t w = idx[mid];
-                    if (w == v) { found = true; break; }
-                    if (w < v) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (!found) f |= 16u;
-            }
-        }
-        if (f) atomicOr(bad, f);
+__global__ void k_check_entries(const Off* off, const int32_t* src, const int32_t* idx, int64_t nnz, int64_t n,
+                                unsigned int* bad) {
+    unsigned int f = 0;
+    GRID_STRIDE(p, nnz) {
+        const int32_t v = src[p], u = idx[p];
+        if (u < 0 || u >= n) f |= 2u;
+        if (u == v) f |= 4u;
+        if (p > static_cast<int64_t>(off[v]) && idx[p - 1] >= u) f |= 8u;
     }
+    if (f) atomicOr(bad, f);
+}
+
+// (v,u) stored => (u,v) stored, by binary search in row u (rows sorted).
+template <class Off>
+__global__ void k_check_symmetry(const Off* off, const int32_t* src, const int32_t* idx, int64_t nnz,
+                                 unsigned int* bad) {
+    unsigned int f = 0;
+    GRID_STRIDE(p, nnz) {
+        const int32_t v = src[p], u = idx[p];
+        int64_t lo = off[u], hi = off[u + 1];
+        bool found = false;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const int32_t w = idx[mid];
+            if (w == v) {
+                found = true;
+                break;
+            }
+            if (w < v) lo = mid + 1;
+            else hi = mid;
+        }
+        if (!found) f |= 16u;
+    }
+    if (f) atomicOr(bad, f);
 }
 
 // ---------------------------------------------------------------- host helpers
@@ -321,25 +347,75 @@ int64_t build_coarse(Ctx* c, const int32_t* src, const int32_t* idx, int64_t nnz
     return nnz_next;
 }
 
+// Row of every entry (one wave per vertex streams its row).
 template <class Off>
-void coarsen_one(Ctx* c, Level& L, Level& next) {
+DevBuf<int32_t> expand_rows(Ctx* c, const Off* off, int64_t n, int64_t nnz) {
+    DevBuf<int32_t> src(c, std::max<int64_t>(nnz, 1));
+    if (nnz > 0 && n > 0) {
+        hipLaunchKernelGGL((k_expand_rows<Off>), grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, off, n,
+                           src.p);
+        GOSH_HIP(hipGetLastError());
+    }
+    return src;
+}
+
+unsigned int read_flags(Ctx* c, unsigned int* bad) {
+    unsigned int h = 0;
+    GOSH_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    GOSH_HIP(hipStreamSynchronize(c->stream));
+    return h;
+}
+
+// Structure checks of a caller's CSR; returns the row of every entry.
+template <class Off>
+DevBuf<int32_t> validate_structure(Ctx* c, const Off* off, const int32_t* idx, int64_t n, int64_t nnz,
+                                   bool symmetry) {
+    unsigned int* bad = reinterpret_cast<unsigned int*>(scratch_u64(c, 3));
+    GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
+    hipLaunchKernelGGL((k_check_offsets<Off>), grid_for(n), dim3(kThreads), 0, c->stream, off, n, nnz, bad);
+    GOSH_HIP(hipGetLastError());
+    GOSH_REQUIRE(read_flags(c, bad) == 0, GOSH_E_BAD_GRAPH,
+                 "offsets must start at 0, end at nnz and never decrease");
+    DevBuf<int32_t> src = expand_rows(c, off, n, nnz);
+    if (nnz > 0) {
+        hipLaunchKernelGGL((k_check_entries<Off>), grid_for(nnz), dim3(kThreads), 0, c->stream, off, src.p, idx,
+                           nnz, n, bad);
+        GOSH_HIP(hipGetLastError());
+        const unsigned int h = read_flags(c, bad);
+        GOSH_REQUIRE(!(h & 2u), GOSH_E_BAD_GRAPH, "neighbour index out of range");
+        GOSH_REQUIRE(!(h & 4u), GOSH_E_BAD_GRAPH, "self-loop");
+        GOSH_REQUIRE(!(h & 8u), GOSH_E_BAD_GRAPH, "row not strictly ascending (unsorted or duplicate)");
+        if (symmetry) {
+            hipLaunchKernelGGL((k_check_symmetry<Off>), grid_for(nnz), dim3(kThreads), 0, c->stream, off, src.p,
+                               idx, nnz, bad);
+            GOSH_HIP(hipGetLastError());
+            GOSH_REQUIRE(!(read_flags(c, bad) & 16u), GOSH_E_BAD_GRAPH, "graph is not symmetric");
+        }
+    }
+    return src;
+}
+
+template <class Off>
+void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     const int64_t n = L.n, nnz = L.nnz;
     const Off* off = static_cast<const Off*>(L.offsets);
     const int32_t* idx = L.indices;
 
-    // degrees, eligibility and the processing order pi
+    // degrees, eligibility (hub^2 restriction) and the processing order pi:
+    // a stable radix sort of the vertices on maxdeg - deg keeps ties in id order
     DevBuf<uint8_t> light(c, n);
     DevBuf<int64_t> deg(c, n);
-    GOSH_HIP(hipMemsetAsync(c->scratch, 0, 64, c->stream));
+    GOSH_HIP(hipMemsetAsync(scratch_u64(c, 0), 0, 8, c->stream));
     hipLaunchKernelGGL((k_degree<Off>), grid_for(n), dim3(kThreads), 0, c->stream, off, n, nnz,
                        light.p, deg.p, scratch_u64(c, 0), nullptr);
     GOSH_HIP(hipGetLastError());
-    const uint64_t maxdeg = read_u64(c, scratch_u64(c, 0));
     DevBuf<uint32_t> key(c, n), key_tmp(c, n), perm(c, n), perm_tmp(c, n);
-    hipLaunchKernelGGL(k_sort_keys, grid_for(n), dim3(kThreads), 0, c->stream, deg.p, n, maxdeg, key.p,
-                       perm.p);
+    hipLaunchKernelGGL(k_sort_keys, grid_for(n), dim3(kThreads), 0, c->stream, deg.p, n,
+                       reinterpret_cast<const unsigned long long*>(scratch_u64(c, 0)), key.p, perm.p);
     GOSH_HIP(hipGetLastError());
-    radix_sort_u32(c, key.p, key_tmp.p, perm.p, perm_tmp.p, n, bits_for(maxdeg));
+    // deg <= nnz/1 < 2^bits_for(max(n-1, nnz)) bounds maxdeg - deg
+    radix_sort_u32(c, key.p, key_tmp.p, perm.p, perm_tmp.p, n,
+                   bits_for(static_cast<uint64_t>(std::min<int64_t>(std::max<int64_t>(n - 1, 0), nnz))));
     key_tmp.reset();
     perm_tmp.reset();
     key.reset();
@@ -348,62 +424,44 @@ void coarsen_one(Ctx* c, Level& L, Level& next) {
     hipLaunchKernelGGL(k_rank_from_perm, grid_for(n), dim3(kThreads), 0, c->stream, perm.p, n, rank.p);
     GOSH_HIP(hipGetLastError());
 
-    // row of every entry, and the eligible entries towards earlier vertices
-    DevBuf<int32_t> src(c, std::max<int64_t>(nnz, 1));
-    if (nnz > 0) {
-        hipLaunchKernelGGL((k_expand_rows<Off>), grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream,
-                           off, n, src.p);
-        GOSH_HIP(hipGetLastError());
-    }
-    int64_t m = 0;
-    DevBuf<int2> low;
+    // row of every entry, and each vertex's eligible earlier neighbours
+    DevBuf<int32_t> src_own;
+    if (!src_in) src_own = expand_rows(c, off, n, nnz);
+    const int32_t* src = src_in ? src_in->p : src_own.p;
+    DevBuf<int32_t> lower(c, std::max<int64_t>(nnz, 1));
+    DevBuf<int64_t> lstart(c, n + 1);
     {
         DevBuf<int32_t> flag(c, std::max<int64_t>(nnz, 1));
         DevBuf<int64_t> pos(c, std::max<int64_t>(nnz, 1));
         if (nnz > 0) {
-            hipLaunchKernelGGL(k_flag_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src.p, idx, nnz,
+            hipLaunchKernelGGL(k_flag_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz,
                                light.p, rank.p, flag.p);
             GOSH_HIP(hipGetLastError());
-            scan_i32_to_i64(c, flag.p, pos.p, nnz, &m);
-        }
-        low = DevBuf<int2>(c, std::max<int64_t>(m, 1));
-        if (m > 0) {
-            hipLaunchKernelGGL(k_write_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src.p, idx, nnz,
-                               flag.p, pos.p, low.p);
+            scan_i32_to_i64(c, flag.p, pos.p, nnz, nullptr);
+            hipLaunchKernelGGL(k_write_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, flag.p,
+                               pos.p, lower.p);
             GOSH_HIP(hipGetLastError());
         }
+        hipLaunchKernelGGL((k_lower_starts<Off>), grid_for(n + 1), dim3(kThreads), 0, c->stream, off, n, nnz,
+                           flag.p, pos.p, lstart.p);
+        GOSH_HIP(hipGetLastError());
     }
+    light.reset();
 
-    // hub selection rounds
-    DevBuf<uint8_t> state(c, n), saw_in(c, n), saw_pending(c, n);
+    // hub selection rounds; each round decides at least the earliest
+    // undecided vertex, so the loop ends
+    DevBuf<uint8_t> state(c, n);
     fill(c, state.p, n, 0);
-    fill(c, saw_in.p, n, 0);
-    fill(c, saw_pending.p, n, 0);
     for (int64_t round = 0;; ++round) {
         GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
-        if (m > 0) {
-            hipLaunchKernelGGL(k_round_edges, grid_for(m), dim3(kThreads), 0, c->stream, low.p, m, state.p,
-                               saw_in.p, saw_pending.p);
-            GOSH_HIP(hipGetLastError());
-        }
         GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
-        hipLaunchKernelGGL(k_round_vertices, grid_for(n), dim3(kThreads), 0, c->stream, n, state.p, saw_in.p,
-                           saw_pending.p, scratch_u64(c, 1));
+        hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                           scratch_u64(c, 1));
         GOSH_HIP(hipGetLastError());
         if (read_u64(c, scratch_u64(c, 1)) == 0) break;
     }
-    saw_in.reset();
-    saw_pending.reset();
 
-    // each marked vertex joins the earliest hub among its eligible earlier neighbours
-    DevBuf<int32_t> best(c, n);
-    fill(c, best.p, n, 0x7F);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_best_hub, grid_for(m), dim3(kThreads), 0, c->stream, low.p, m, state.p, rank.p,
-                           best.p);
-        GOSH_HIP(hipGetLastError());
-    }
-    low.reset();
+    // cluster ids: hubs counted in pi order
     DevBuf<int32_t> hf(c, n);
     DevBuf<int64_t> cid(c, n);
     hipLaunchKernelGGL(k_hub_flags_by_rank, grid_for(n), dim3(kThreads), 0, c->stream, perm.p, n, state.p,
@@ -413,123 +471,82 @@ void coarsen_one(Ctx* c, Level& L, Level& next) {
     scan_i32_to_i64(c, hf.p, cid.p, n, &n_next);
     hf.reset();
     L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
-    L.clsz = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * std::max<int64_t>(n_next, 1)));
-    fill(c, L.clsz, n_next, 0);
     unsigned int* bad = reinterpret_cast<unsigned int*>(scratch_u64(c, 4));
     GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, state.p, rank.p, best.p,
-                       cid.p, L.map, L.clsz, bad);
+    hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                       rank.p, cid.p, L.map, bad);
     GOSH_HIP(hipGetLastError());
-    GOSH_REQUIRE(read_u64(c, scratch_u64(c, 4)) == 0, GOSH_E_BAD_GRAPH,
-                 "coarsening found a vertex without a cluster (graph not symmetric?)");
     cid.reset();
-    best.reset();
     state.reset();
     rank.reset();
     perm.reset();
-    light.reset();
+    lower.reset();
+    lstart.reset();
 
     // coarse graph: distinct pairs (map v, map u), map v != map u, rows ascending
     void* noff = nullptr;
     int32_t* nidx = nullptr;
     int64_t nnz_next;
     if (2 * std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(n_next - 1, 0)))) <= 32)
-        nnz_next = build_coarse<uint32_t>(c, src.p, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+        nnz_next = build_coarse<uint32_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
     else
-        nnz_next = build_coarse<uint64_t>(c, src.p, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+        nnz_next = build_coarse<uint64_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+    // the assignment flag was written before the syncs inside build_coarse
+    GOSH_REQUIRE(read_flags(c, bad) == 0, GOSH_E_BAD_GRAPH,
+                 "coarsening left a vertex without a cluster (graph not symmetric?)");
     next.n = n_next;
     next.nnz = nnz_next;
     next.off64 = L.off64;
     next.offsets = next.own_offsets = noff;
     next.indices = next.own_indices = nidx;
-    next.n_deg0 = count_isolated(c, next);
+    next.n_deg0 = -1;
 }
 
 }  // namespace
 
 int64_t count_isolated(Ctx* c, const Level& L) {
-    if (L.n == 0) return 0;
-    GOSH_HIP(hipMemsetAsync(scratch_u64(c, 2), 0, 8, c->stream));
-    if (L.off64)
-        hipLaunchKernelGGL((k_degree<int64_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
-                           static_cast<const int64_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
-                           scratch_u64(c, 2));
-    else
-        hipLaunchKernelGGL((k_degree<int32_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
-                           static_cast<const int32_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
-                           scratch_u64(c, 2));
-    GOSH_HIP(hipGetLastError());
-    return static_cast<int64_t>(read_u64(c, scratch_u64(c, 2)));
+    if (L.n_deg0 >= 0) return L.n_deg0;
+    int64_t cnt = 0;
+    if (L.n > 0) {
+        GOSH_HIP(hipMemsetAsync(scratch_u64(c, 2), 0, 8, c->stream));
+        if (L.off64)
+            hipLaunchKernelGGL((k_degree<int64_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
+                               static_cast<const int64_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
+                               scratch_u64(c, 2));
+        else
+            hipLaunchKernelGGL((k_degree<int32_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
+                               static_cast<const int32_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
+                               scratch_u64(c, 2));
+        GOSH_HIP(hipGetLastError());
+        cnt = static_cast<int64_t>(read_u64(c, scratch_u64(c, 2)));
+    }
+    const_cast<Level&>(L).n_deg0 = cnt;
+    return cnt;
+}
+
+const int32_t* cluster_sizes(Ctx* c, const Level& L, int64_t n_next) {
+    if (!L.clsz && L.map) {
+        Level& M = const_cast<Level&>(L);
+        M.clsz = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * std::max<int64_t>(n_next, 1)));
+        fill(c, M.clsz, n_next, 0);
+        if (L.n > 0) {
+            hipLaunchKernelGGL(k_cluster_sizes, grid_for(L.n), dim3(kThreads), 0, c->stream, L.map, L.n, M.clsz);
+            GOSH_HIP(hipGetLastError());
+        }
+    }
+    return L.clsz;
 }
 
 void validate_csr(Ctx* c, const gosh_csr* g, bool symmetry) {
     GOSH_REQUIRE(g && g->n >= 0 && g->nnz >= 0, GOSH_E_INVALID_ARG, "bad csr shape");
-    GOSH_REQUIRE(g->offsets && (g->nnz == 0 || g->indices), GOSH_E_INVALID_ARG, "null csr pointer");
-    GOSH_REQUIRE(g->offsets_is_i64 || g->nnz <= INT32_MAX, GOSH_E_INVALID_ARG,
-                 "nnz needs int64 offsets");
-    GOSH_REQUIRE(g->n < INT32_MAX, GOSH_E_UNSUPPORTED, "vertex ids are int32");
-    int64_t first = 0, last = 0;
-    if (g->offsets_is_i64) {
-        const int64_t* o = static_cast<const int64_t*>(g->offsets);
-        GOSH_HIP(hipMemcpyAsync(&first, o, 8, hipMemcpyDeviceToHost, c->stream));
-        GOSH_HIP(hipMemcpyAsync(&last, o + g->n, 8, hipMemcpyDeviceToHost, c->stream));
-    } else {
-        int32_t f32 = 0, l32 = 0;
-        const int32_t* o = static_cast<const int32_t*>(g->offsets);
-        GOSH_HIP(hipMemcpyAsync(&f32, o, 4, hipMemcpyDeviceToHost, c->stream));
-        GOSH_HIP(hipMemcpyAsync(&l32, o + g->n, 4, hipMemcpyDeviceToHost, c->stream));
-        GOSH_HIP(hipStreamSynchronize(c->stream));
-        first = f32;
-        last = l32;
+    if (g->n == 0) {
+        GOSH_REQUIRE(g->nnz == 0, GOSH_E_BAD_GRAPH, "an empty graph has no entries");
+        return;
     }
-    GOSH_HIP(hipStreamSynchronize(c->stream));
-    GOSH_REQUIRE(first == 0 && last == g->nnz, GOSH_E_BAD_GRAPH, "offsets must run from 0 to nnz");
-    if (g->n == 0) return;
-    unsigned int* bad = reinterpret_cast<unsigned int*>(scratch_u64(c, 3));
-    unsigned int h = 0;
-    GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
     if (g->offsets_is_i64)
-        hipLaunchKernelGGL((k_check_offsets<int64_t>), grid_for(g->n), dim3(kThreads), 0, c->stream,
-                           static_cast<const int64_t*>(g->offsets), g->n, g->nnz, bad);
+        validate_structure(c, static_cast<const int64_t*>(g->offsets), g->indices, g->n, g->nnz, symmetry);
     else
-        hipLaunchKernelGGL((k_check_offsets<int32_t>), grid_for(g->n), dim3(kThreads), 0, c->stream,
-                           static_cast<const int32_t*>(g->offsets), g->n, g->nnz, bad);
-    GOSH_HIP(hipGetLastError());
-    GOSH_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
-    GOSH_HIP(hipStreamSynchronize(c->stream));
-    GOSH_REQUIRE(h == 0, GOSH_E_BAD_GRAPH, "offsets decrease or leave [0, nnz]");
-    GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
-    if (g->offsets_is_i64)
-        hipLaunchKernelGGL((k_validate<int64_t>), grid_for(g->n, kThreads / 64), dim3(kThreads), 0,
-                           c->stream, static_cast<const int64_t*>(g->offsets), g->indices, g->n,
-                           0, bad);
-    else
-        hipLaunchKernelGGL((k_validate<int32_t>), grid_for(g->n, kThreads / 64), dim3(kThreads), 0,
-                           c->stream, static_cast<const int32_t*>(g->offsets), g->indices, g->n,
-                           0, bad);
-    GOSH_HIP(hipGetLastError());
-    GOSH_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
-    GOSH_HIP(hipStreamSynchronize(c->stream));
-    GOSH_REQUIRE(!(h & 1u), GOSH_E_BAD_GRAPH, "offsets decrease");
-    GOSH_REQUIRE(!(h & 2u), GOSH_E_BAD_GRAPH, "neighbour index out of range");
-    GOSH_REQUIRE(!(h & 4u), GOSH_E_BAD_GRAPH, "self-loop");
-    GOSH_REQUIRE(!(h & 8u), GOSH_E_BAD_GRAPH, "row not strictly ascending (unsorted or duplicate)");
-    if (symmetry) {
-        // only run once the structure is known to be in range
-        GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
-        if (g->offsets_is_i64)
-            hipLaunchKernelGGL((k_validate<int64_t>), grid_for(g->n, kThreads / 64), dim3(kThreads), 0,
-                               c->stream, static_cast<const int64_t*>(g->offsets), g->indices, g->n, 1,
-                               bad);
-        else
-            hipLaunchKernelGGL((k_validate<int32_t>), grid_for(g->n, kThreads / 64), dim3(kThreads), 0,
-                               c->stream, static_cast<const int32_t*>(g->offsets), g->indices, g->n, 1,
-                               bad);
-        GOSH_HIP(hipGetLastError());
-        GOSH_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
-        GOSH_HIP(hipStreamSynchronize(c->stream));
-        GOSH_REQUIRE(!(h & 16u), GOSH_E_BAD_GRAPH, "graph is not symmetric");
-    }
+        validate_structure(c, static_cast<const int32_t*>(g->offsets), g->indices, g->n, g->nnz, symmetry);
 }
 
 void coarsen(Ctx* c, const gosh_csr* g0, int64_t threshold, double ratio, gosh_levels* out) {
@@ -539,15 +556,25 @@ void coarsen(Ctx* c, const gosh_csr* g0, int64_t threshold, double ratio, gosh_l
     L0.off64 = g0->offsets_is_i64 != 0;
     L0.offsets = g0->offsets;
     L0.indices = g0->indices;
-    L0.n_deg0 = count_isolated(c, L0);
+    L0.n_deg0 = -1;
     out->lv.push_back(L0);
-    if (L0.n == 0) return;
+    if (L0.n == 0) {
+        GOSH_REQUIRE(L0.nnz == 0, GOSH_E_BAD_GRAPH, "an empty graph has no entries");
+        return;
+    }
+    // the caller's graph is checked before any kernel relies on it; the
+    // row expansion made for the check is reused by the first level
+    DevBuf<int32_t> src0 = L0.off64
+        ? validate_structure(c, static_cast<const int64_t*>(L0.offsets), L0.indices, L0.n, L0.nnz, false)
+        : validate_structure(c, static_cast<const int32_t*>(L0.offsets), L0.indices, L0.n, L0.nnz, false);
     constexpr int kMaxLevels = 128;
     while (static_cast<int>(out->lv.size()) < kMaxLevels) {
         Level next;
         Level& cur = out->lv.back();
-        if (cur.off64) coarsen_one<int64_t>(c, cur, next);
-        else coarsen_one<int32_t>(c, cur, next);
+        DevBuf<int32_t>* src = out->lv.size() == 1 ? &src0 : nullptr;
+        if (cur.off64) coarsen_one<int64_t>(c, cur, next, src);
+        else coarsen_one<int32_t>(c, cur, next, src);
+        if (src) src0.reset();
         const int64_t n_prev = cur.n;
         out->lv.push_back(next);
         if (!(next.n >= threshold && static_cast<double>(next.n) <= ratio * static_cast<double>(n_prev)))

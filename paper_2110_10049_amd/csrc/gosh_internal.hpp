@@ -90,7 +90,7 @@ struct Level {
     int32_t* own_indices = nullptr;
     int32_t* map = nullptr;            // map to level+1 (owned), null on the coarsest
     int32_t* clsz = nullptr;           // sizes of level+1's clusters (owned)
-    int64_t n_deg0 = 0;                // vertices without neighbours
+    int64_t n_deg0 = -1;               // vertices without neighbours (-1: not yet counted)
 };
 
 }  // namespace gosh
@@ -114,7 +114,8 @@ namespace gosh {
 // (implemented in coarsen.hip / train.hip / prolong.hip)
 void validate_csr(Ctx* c, const gosh_csr* g, bool symmetry);
 void coarsen(Ctx* c, const gosh_csr* g0, int64_t threshold, double ratio, gosh_levels* out);
-int64_t count_isolated(Ctx* c, const Level& L);
+int64_t count_isolated(Ctx* c, const Level& L);           // cached in L
+const int32_t* cluster_sizes(Ctx* c, const Level& L, int64_t n_next);  // computed on first use
 void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d,
                  int epochs, float lr, int k, uint32_t tag, uint64_t* updates_dev);
 void draw_samples(Ctx* c, const Level& L, int32_t level, int32_t epoch, int k, uint32_t tag,

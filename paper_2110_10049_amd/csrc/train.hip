@@ -24,6 +24,7 @@
 // so lane gl draws exactly one block (block gl) per row update.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.hpp"
@@ -66,7 +67,12 @@ enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2 };
 // BF16 rows receive, per 32-bit word, the exact difference between the
 // stochastically rounded new value and the value this visit started from,
 // through the packed BF16 atomic add: uncontended, the stored row becomes
-// exactly the rounded value; contended, the concurrent changes add up.
+// exactly the rounded value (the difference of two nearby BF16 values is
+// itself a BF16 value); contended, the concurrent changes add up in value
+// space.  (Adding bit-pattern differences with integer atomics would be
+// faster but wraps through the sign when many concurrent updates move one
+// element across zero.)  The L2 atomic units sustain about half the
+// bandwidth of plain stores, so they bound the training kernel.
 template <bool BF16>
 struct RowIO;
 
@@ -314,8 +320,20 @@ __global__ void k_draw(TrainParams P, int32_t* out) {
     }
 }
 
-__global__ void k_add_u64(unsigned long long* p, unsigned long long v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(p, v);
+// Adds the UpdateEmbed calls of `epochs` epochs without self-negatives:
+// one positive per vertex with neighbours plus k negatives per vertex
+// (negatives equal to the source are subtracted by the training kernel).
+template <class Off>
+__global__ void k_add_updates(const Off* off, int64_t n, int k, int epochs, unsigned long long* p) {
+    unsigned long long cnt = 0;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+         v += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        cnt += (off[v + 1] != off[v]) ? 1ull : 0ull;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    unsigned long long add = ((threadIdx.x & 63) == 0) ? cnt * static_cast<unsigned long long>(epochs) : 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        add += static_cast<unsigned long long>(k) * static_cast<unsigned long long>(n) * epochs;
+    if (add) atomicAdd(p, add);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -409,10 +427,14 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
         GOSH_HIP(hipGetLastError());
     }
     if (updates_dev) {
-        const unsigned long long per_epoch =
-            static_cast<unsigned long long>(L.n - L.n_deg0) + static_cast<unsigned long long>(k) * L.n;
-        hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, c->stream,
-                           reinterpret_cast<unsigned long long*>(updates_dev), per_epoch * epochs);
+        const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(L.n, 256), 1024));
+        auto* cnt = reinterpret_cast<unsigned long long*>(updates_dev);
+        if (L.off64)
+            hipLaunchKernelGGL(k_add_updates<int64_t>, dim3(blocks), dim3(256), 0, c->stream,
+                               static_cast<const int64_t*>(L.offsets), L.n, k, epochs, cnt);
+        else
+            hipLaunchKernelGGL(k_add_updates<int32_t>, dim3(blocks), dim3(256), 0, c->stream,
+                               static_cast<const int32_t*>(L.offsets), L.n, k, epochs, cnt);
         GOSH_HIP(hipGetLastError());
     }
 }

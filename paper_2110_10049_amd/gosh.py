@@ -52,7 +52,7 @@ _SIGNATURES = [
     ("gosh_level_shape", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("gosh_level_csr", C.c_int, [_P, C.c_int32, C.POINTER(gosh_csr)]),
     ("gosh_level_map", C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
-    ("gosh_level_copy_out", C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
+    ("gosh_level_copy_out", C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P]),
     ("gosh_epoch_schedule", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     ("gosh_train", C.c_int, [_P, _P, C.c_int32, _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
                              C.c_int32, C.c_uint32, _P]),
@@ -199,8 +199,16 @@ class Levels:
         mp = np.zeros(max(n, 1), np.int32) if want_map else None
         self.ctx.check(lib().gosh_level_copy_out(
             self.ctx.h, self.h, level, off.ctypes.data, idx.ctypes.data,
-            mp.ctypes.data if mp is not None else None))
+            mp.ctypes.data if mp is not None else None, None))
         return off, idx[:nnz], (mp[:n] if mp is not None else None)
+
+    def cluster_sizes(self, level: int):
+        """Sizes of the clusters of `level` that form the vertices of level+1."""
+        import numpy as np
+        nn, _ = self.shape(level + 1)
+        cs = np.zeros(max(nn, 1), np.int32)
+        self.ctx.check(lib().gosh_level_copy_out(self.ctx.h, self.h, level, None, None, None, cs.ctypes.data))
+        return cs[:nn]
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -51,6 +51,32 @@ def test_config1_train_graph(gctx, orc):
     assert lv.count() >= 3
 
 
+def test_cluster_sizes(gctx, orc):
+    from paper_2110_10049_amd import gosh as G
+    off, idx = rmat_csr(11, 8, 5)
+    lv = G.gosh_coarsen(gctx, G.CSR.from_numpy(off, idx), 8)
+    _, maps = orc.coarsen_levels(off, idx, 8)
+    for i, mp in enumerate(maps):
+        nn = lv.shape(i + 1)[0]
+        assert np.array_equal(lv.cluster_sizes(i), np.bincount(mp, minlength=nn))
+
+
+def test_coarsen_and_single_reject_bad_graphs(gctx):
+    from paper_2110_10049_amd import gosh as G
+    bad = {
+        "self-loop": (np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32)),
+        "out of range": (np.array([0, 1, 2], np.int64), np.array([1, 5], np.int32)),
+        "offsets": (np.array([0, 3, 1, 2], np.int64), np.array([1, 2], np.int32)),
+        "last offset": (np.array([0, 1, 1], np.int64), np.array([1, 0], np.int32)),
+    }
+    for name, (o, x) in bad.items():
+        g = G.CSR.from_numpy(o, x)
+        for fn in (lambda: G.gosh_coarsen(gctx, g, 1), lambda: G.gosh_levels_single(gctx, g)):
+            with pytest.raises(G.GoshError) as ei:
+                fn()
+            assert ei.value.status == "E_BAD_GRAPH", name
+
+
 def test_int64_offsets(gctx, orc):
     off, idx = rmat_csr(10, 8, 7)
     _compare(gctx, orc, off, idx, threshold=16, off64=True)
