@@ -34,6 +34,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_bf16_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per level-0 launch from the committed counter summary, or
+    None if the training kernel source changed since it was measured."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        fields = dict(l.strip().split(": ", 1) for l in txt.splitlines() if l.startswith("    ") and ": " in l
+                      and l.strip().split(": ", 1)[0] in ("kernel_source", "kernel_source_sha256",
+                                                          "traffic_bytes_per_launch"))
+        src = os.path.join(ROOT, fields["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["kernel_source_sha256"]:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 WORKLOADS = {
     # name: (scale, edge factor, d, k, epochs, threshold)
@@ -56,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-epochs", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
@@ -78,6 +98,13 @@ def main():
     sp = split_edges(off, idx, seeds["split"])
     log(f"graph ready: |V_train|={sp.n} nnz={len(sp.indices)} ({time.time() - t0:.1f}s)")
 
+    if a.copy_calibration_mib:
+        nb = a.copy_calibration_mib << 20
+        src_buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     ctx = G.Context(0, seed=seeds["philox"])
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
@@ -128,13 +155,13 @@ def main():
     e0 = bf["schedule"][0]
     o = 4   # int32 offsets
 
-    def roof(r, b):
+    def roof(r, b, traffic=None):
         per_src = 2 * d * b * (2 + k) + 2 * o + 4
         bytes_launch = n0 * per_src
         launch_s = r["level0_ms"] / 1e3 / e0
         ach = bytes_launch / launch_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_train level 0", "bytes_per_launch": bytes_launch,
                 "launch_us": round(launch_s * 1e6, 2)}
 
@@ -151,7 +178,7 @@ def main():
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
                    "updates_per_step": bf["updates_per_step"]},
-        "roofline": roof(bf, 2),
+        "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" else None),
         "train_ms_per_step": round(bf["train_ms"], 3),
     }
     if f32 is not None:
