@@ -160,6 +160,40 @@ gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void
                        gosh_dtype dt, int32_t d, int32_t epochs, float lr, int32_t k,
                        uint32_t tag, uint64_t* updates_dev);
 
+/* One independent training job of gosh_train_batched. */
+typedef struct {
+    gosh_csr g;          /* the job's graph (device, borrowed; must satisfy the graph
+                            convention, e.g. a level of gosh_coarsen or a graph accepted
+                            by gosh_validate_csr)                                      */
+    void* emb;           /* device [g.n, d] rows of the call's dtype, updated in place */
+    int32_t epochs;      /* epochs of this job (its lr decays over these)              */
+    float lr;            /* initial learning rate                                      */
+    int32_t level;       /* level field of the job's Philox counters (0..255)          */
+    uint32_t tag;        /* tag field of the job's Philox counters (24 bits)           */
+} gosh_job;
+
+typedef enum {
+    GOSH_BATCH_AUTO = 0,        /* autotuned per (dtype, d, k, size class), cached  */
+    GOSH_BATCH_PERSISTENT = 1,  /* one persistent launch, per-job epoch barriers    */
+    GOSH_BATCH_EPOCH_GRAPH = 2  /* one launch per epoch round, chained in a hipGraph */
+} gosh_batch_mode;
+
+/* Trains `njobs` independent jobs (Algorithm 3 on each job's graph, Section
+ * 3.1): every job gets exactly the semantics of gosh_train on its own graph
+ * with its own epochs, lr, level and tag (its epochs never overlap; jobs do
+ * not wait for one another).  d, k and dtype are shared.  Meant for many
+ * small graphs and for small coarse levels, where one launch per epoch and
+ * graph would leave the device mostly idle.  GOSH_BATCH_AUTO times the
+ * executions on a two-epoch dry run over scratch copies of the rows the
+ * first time a (dtype, d, k, size class) is seen and caches the winner (also
+ * appended to the file named by the GOSH_TUNE_CACHE environment variable).
+ * chosen_out (may be NULL) receives {mode, blocks per CU, chunk length} of
+ * the execution used.  Synchronous.  Errors as gosh_train; a scheduling
+ * failure inside the persistent launch returns GOSH_E_DEVICE. */
+gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs,
+                               gosh_dtype dt, int32_t d, int32_t k, gosh_batch_mode mode,
+                               uint64_t* updates_dev, int32_t* chosen_out);
+
 /* ExpandEmbedding (Algorithm 2): fine[v] = coarse[map_{fine_level}[v]] for
  * every vertex v of level fine_level.  coarse_emb: [n_{fine_level+1}, d],
  * fine_emb: [n_{fine_level}, d], both device, same dtype.  Asynchronous. */

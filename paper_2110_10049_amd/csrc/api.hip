@@ -389,6 +389,20 @@ gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void
     });
 }
 
+gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs, gosh_dtype dt, int32_t d,
+                               int32_t k, gosh_batch_mode mode, uint64_t* updates_dev, int32_t* chosen_out) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        Ctx* c = &ctx->c;
+        set_device(c);
+        gosh::train_batched(c, jobs_host, njobs, dt, d, k, static_cast<int>(mode), updates_dev, chosen_out);
+        GOSH_HIP(hipStreamSynchronize(c->stream));
+        unsigned int err = 0;
+        GOSH_HIP(hipMemcpy(&err, static_cast<char*>(c->scratch) + 256, 4, hipMemcpyDeviceToHost));
+        GOSH_REQUIRE(err == 0, GOSH_E_DEVICE, "batched training: a task waited beyond the spin limit");
+    });
+}
+
 gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_level, const void* coarse_emb,
                          void* fine_emb, gosh_dtype dt, int32_t d) {
     if (!ctx) return GOSH_E_INVALID_ARG;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <array>
 #include <map>
 #include <set>
 #include <stdexcept>
@@ -47,6 +48,9 @@ struct Ctx {
     std::map<void*, size_t> live;
     // small device scratch for counters and flags
     void* scratch = nullptr;   // 4 KiB
+    // batched-training autotune cache: key -> (mode, blocks per CU, chunk iterations)
+    std::map<std::string, std::array<int, 3>> tune;
+    bool tune_loaded = false;
 
     void* alloc(size_t bytes);
     void free(void* p);
@@ -125,6 +129,8 @@ void update_batch(Ctx* c, void* emb, gosh_dtype dt, int d, int64_t n_rows, int n
                   uint32_t tag, int32_t epoch);
 void prolong_copy(Ctx* c, const Level& fine, const void* coarse, void* fine_emb, gosh_dtype dt,
                   int d);
+void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
+                   uint64_t* updates_dev, int32_t* chosen);
 void free_level(Ctx* c, Level& L);
 
 }  // namespace gosh

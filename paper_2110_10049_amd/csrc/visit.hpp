@@ -1,0 +1,275 @@
+// Per-source visit of TrainInGPU (Algorithm 3) with UpdateEmbed (Algorithm 1)
+// for gfx950, shared by the per-epoch trainer and the batched trainer.  See
+// train.hip for the lane layout and the write discipline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_util.hpp"
+
+namespace gosh {
+namespace train_detail {
+
+
+constexpr int kEPL = 8;       // row elements per lane
+constexpr int kBlock = 256;   // 4 waves
+
+struct TrainParams {
+    const void* offsets;
+    const int32_t* indices;
+    int64_t n;                // vertices of the level (negatives are drawn from [0, n))
+    int64_t nnz;              // entries of the level's CSR
+    void* emb;
+    int64_t n_rows;           // rows addressable in emb
+    float lr;
+    int k;
+    uint32_t key0, key1;
+    uint32_t epoch;
+    uint32_t w2;              // level | tag << 8
+    unsigned long long* updates;   // optional executed-update counter
+    const int32_t* src_list;       // explicit-sample mode
+    const int32_t* samples;
+    int64_t nsrc;
+};
+
+enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
+
+// Row access.  A lane of the group of L = d/8 lanes owns row elements
+// gl + L*i (FP32) or 32-bit words gl + L*i (BF16, two elements each), so
+// every load and every atomic instruction of a group covers one contiguous
+// run of the row.
+//
+// Writes are atomic: sources of an epoch run concurrently and share rows, and
+// a plain read-modify-write store would drop every concurrent update but the
+// last one -- on small levels, where a whole epoch is in flight at once,
+// nearly all of them.  FP32 rows receive their changes with atomic adds.
+// BF16 rows receive, per 32-bit word, the exact difference between the
+// stochastically rounded new value and the value this visit started from,
+// through the packed BF16 atomic add: uncontended, the stored row becomes
+// exactly the rounded value (the difference of two nearby BF16 values is
+// itself a BF16 value); contended, the concurrent changes add up in value
+// space.  (Adding bit-pattern differences with integer atomics would be
+// faster but wraps through the sign when many concurrent updates move one
+// element across zero.)  The L2 atomic units sustain about half the
+// bandwidth of plain stores, so they bound the training kernel.
+template <bool BF16>
+struct RowIO;
+
+template <>
+struct RowIO<false> {
+    using Elem = float;
+    template <int L, bool COH>
+    __device__ static void load(const float* M, int64_t row, int gl, float (&x)[kEPL]) {
+        const float* p = M + row * (L * kEPL) + gl;
+#pragma unroll
+        for (int i = 0; i < kEPL; ++i) {
+            if constexpr (COH)
+                x[i] = __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p + L * i),
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            else
+                x[i] = p[L * i];
+        }
+    }
+    template <int L>
+    __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[kEPL]) {
+        float* p = M + row * (L * kEPL) + gl;
+#pragma unroll
+        for (int i = 0; i < kEPL; ++i)
+            __hip_atomic_fetch_add(p + L * i, dx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+typedef __bf16 __attribute__((ext_vector_type(2))) bf16x2_t;
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <>
+struct RowIO<true> {
+    using Elem = uint16_t;
+    template <int L, bool COH>
+    __device__ static void load(const uint16_t* M, int64_t row, int gl, float (&x)[kEPL]) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * (L * kEPL)) + gl;
+#pragma unroll
+        for (int i = 0; i < kEPL / 2; ++i) {
+            uint32_t w;
+            if constexpr (COH)
+                w = __hip_atomic_load(p + L * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                w = p[L * i];
+            x[2 * i] = bf16_lo(w);
+            x[2 * i + 1] = bf16_hi(w);
+        }
+    }
+    // cur: the values this visit last saw (exact BF16), v: the FP32 results.
+    // Element h of the lane uses random half h of r.  out: the rounded values.
+    template <int L>
+    __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[kEPL],
+                                  const float (&v)[kEPL], uint4 r, float (&out)[kEPL]) {
+        uint32_t* p = reinterpret_cast<uint32_t*>(M + row * (L * kEPL)) + gl;
+        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < kEPL / 2; ++i) {
+            const uint32_t t0 = bf16_sr(v[2 * i], rw[i] & 0xFFFFu);
+            const uint32_t t1 = bf16_sr(v[2 * i + 1], rw[i] >> 16);
+            out[2 * i] = __uint_as_float(t0 << 16);
+            out[2 * i + 1] = __uint_as_float(t1 << 16);
+            const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
+                               (bf16_rne_bits(out[2 * i + 1] - cur[2 * i + 1]) << 16);
+            if (d != 0u)
+                __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                    (__attribute__((address_space(1))) bf16x2_t*)(p + L * i),
+                    __builtin_bit_cast(bf16x2_t, d));
+        }
+    }
+};
+
+__device__ __forceinline__ float sigmoidf_(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+}
+
+// One source visit: draws (or reads) the samples and applies the updates.
+template <bool BF16, int D, int KMAX, class Off, int MODE>
+__device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool active, int gl) {
+    constexpr int L = D / kEPL;
+    using IO = RowIO<BF16>;
+    using Elem = typename IO::Elem;
+    Elem* M = static_cast<Elem*>(P.emb);
+    const int k = P.k;
+
+    int64_t src = slot;
+    int32_t u[KMAX + 1];
+#pragma unroll
+    for (int t = 0; t <= KMAX; ++t) u[t] = -1;
+
+    if constexpr (MODE == kExplicit) {
+        if (active) {
+            src = P.src_list[slot];
+            active = src >= 0 && src < P.n_rows;
+        }
+        if (active) {
+#pragma unroll
+            for (int t = 0; t <= KMAX; ++t) {
+                if (t <= k) {
+                    const int32_t v = P.samples[slot * (1 + k) + t];
+                    u[t] = (v >= 0 && v < P.n_rows) ? v : -1;
+                }
+            }
+        }
+    } else {
+        if (active) {
+            constexpr int NB = (KMAX + 1 + 3) / 4;
+            uint32_t wd[4 * NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (4 * b <= k) {
+                    const uint4 r = philox10(
+                        make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2, stream_word3(0, 0, b)),
+                        P.key0, P.key1);
+                    wd[4 * b] = r.x; wd[4 * b + 1] = r.y; wd[4 * b + 2] = r.z; wd[4 * b + 3] = r.w;
+                } else {
+                    wd[4 * b] = wd[4 * b + 1] = wd[4 * b + 2] = wd[4 * b + 3] = 0;
+                }
+            }
+            const Off* off = static_cast<const Off*>(P.offsets);
+            const int64_t beg = off[src], end = off[src + 1];
+            // a malformed row is treated as empty instead of read out of bounds
+            const int64_t deg = (beg >= 0 && beg <= end && end <= P.nnz) ? end - beg : 0;
+#pragma unroll
+            for (int t = 1; t <= KMAX; ++t)
+                if (t <= k) u[t] = static_cast<int32_t>(scale_u32(wd[t], P.n));
+            if (deg > 0) {
+                const int32_t pos = P.indices[beg + scale_u32(wd[0], deg)];
+                u[0] = (pos >= 0 && pos < P.n) ? pos : -1;
+            }
+        }
+    }
+    if (!active) return;
+
+    float s[kEPL];
+    float m[KMAX + 1][kEPL];
+    constexpr bool kCoherent = (MODE == kPersistent);
+    IO::template load<L, kCoherent>(M, src, gl, s);
+#pragma unroll
+    for (int t = 0; t <= KMAX; ++t) {
+        if (u[t] >= 0 && u[t] != src) {
+            IO::template load<L, kCoherent>(M, u[t], gl, m[t]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) m[t][e] = 0.0f;
+        }
+    }
+
+    int done = 0;
+    const float lr = P.lr;
+    float s0[kEPL];
+#pragma unroll
+    for (int e = 0; e < kEPL; ++e) s0[e] = s[e];
+#pragma unroll
+    for (int t = 0; t <= KMAX; ++t) {
+        if (t > k) break;
+        const int32_t ut = u[t];
+        if (ut < 0 || ut == src) {
+            if (t > 0 && ut == src && P.updates && gl == 0) atomicAdd(P.updates, ~0ull);  // -1
+            continue;
+        }
+        // a row sampled earlier in this visit continues from its updated value
+#pragma unroll
+        for (int tp = 0; tp < t; ++tp) {
+            if (u[tp] == ut) {
+#pragma unroll
+                for (int e = 0; e < kEPL; ++e) m[t][e] = m[tp][e];
+            }
+        }
+        float x = 0.0f;
+#pragma unroll
+        for (int e = 0; e < kEPL; ++e) x = fmaf(s[e], m[t][e], x);
+        x = group_sum<L>(x);
+        const float b = (t == 0) ? 1.0f : 0.0f;
+        const float g = (b - sigmoidf_(x)) * lr;
+#pragma unroll
+        for (int e = 0; e < kEPL; ++e) s[e] = fmaf(g, m[t][e], s[e]);
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
+                                                   stream_word3(1, static_cast<uint32_t>(t),
+                                                                static_cast<uint32_t>(gl))),
+                                        P.key0, P.key1);
+            float v[kEPL], out[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) v[e] = fmaf(g, s[e], m[t][e]);
+            IO::template commit<L>(M, ut, gl, m[t], v, bits, out);
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) m[t][e] = out[e];
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) {
+                dx[e] = g * s[e];
+                m[t][e] += dx[e];
+            }
+            IO::template add<L>(M, ut, gl, dx);
+        }
+        ++done;
+    }
+    if (done) {
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
+                                                   stream_word3(1, 0xFFu, static_cast<uint32_t>(gl))),
+                                        P.key0, P.key1);
+            float out[kEPL];
+            IO::template commit<L>(M, src, gl, s0, s, bits, out);
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) dx[e] = s[e] - s0[e];
+            IO::template add<L>(M, src, gl, dx);
+        }
+    }
+}
+
+}  // namespace train_detail
+}  // namespace gosh

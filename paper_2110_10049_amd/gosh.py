@@ -32,6 +32,14 @@ class gosh_csr(C.Structure):
                 ("offsets_is_i64", C.c_int32), ("indices", C.c_void_p)]
 
 
+class gosh_job(C.Structure):
+    _fields_ = [("g", gosh_csr), ("emb", C.c_void_p), ("epochs", C.c_int32), ("lr", C.c_float),
+                ("level", C.c_int32), ("tag", C.c_uint32)]
+
+
+GOSH_BATCH_AUTO, GOSH_BATCH_PERSISTENT, GOSH_BATCH_EPOCH_GRAPH = 0, 1, 2
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -56,6 +64,8 @@ _SIGNATURES = [
     ("gosh_epoch_schedule", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     ("gosh_train", C.c_int, [_P, _P, C.c_int32, _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
                              C.c_int32, C.c_uint32, _P]),
+    ("gosh_train_batched", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
+                                     C.c_int, _P, C.POINTER(C.c_int32)]),
     ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32]),
     ("gosh_draw_samples", C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P]),
     ("gosh_update_batch", C.c_int, [_P, _P, C.c_int, C.c_int32, C.c_int64, C.c_int32, _P, _P,
@@ -281,3 +291,23 @@ def gosh_update_batch(ctx: Context, emb: torch.Tensor, src: torch.Tensor, sample
     ctx.check(lib().gosh_update_batch(ctx.h, _dev(emb, name="emb"), _dtype_code(emb), emb.shape[1], emb.shape[0],
                                       src.numel(), _dev(src, torch.int32, "src"),
                                       _dev(samples, torch.int32, "samples"), k, lr, level, tag, epoch))
+
+
+def gosh_train_batched(ctx: Context, jobs, k: int, mode: int = GOSH_BATCH_AUTO,
+                       updates: torch.Tensor | None = None):
+    """jobs: list of (CSR or gosh_csr view, emb tensor, epochs, lr, level, tag).
+    Returns the execution used: (mode, blocks per CU, chunk length)."""
+    if not jobs:
+        return (0, 0, 0)
+    arr = (gosh_job * len(jobs))()
+    dtype = jobs[0][1].dtype
+    d = jobs[0][1].shape[1]
+    for i, (g, emb, epochs, lr, level, tag) in enumerate(jobs):
+        view = g.view if isinstance(g, CSR) else g
+        if emb.dtype != dtype or emb.dim() != 2 or emb.shape[1] != d or emb.shape[0] != view.n:
+            raise ValueError("every job needs a [n, d] embedding of the same dtype and d")
+        arr[i] = gosh_job(view, _dev(emb, name="emb").value, epochs, lr, level, tag)
+    chosen = (C.c_int32 * 3)()
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    ctx.check(lib().gosh_train_batched(ctx.h, arr, len(jobs), _dtype_code(jobs[0][1]), d, k, mode, u, chosen))
+    return tuple(chosen)
