@@ -24,6 +24,9 @@ class EmbedConfig:
     threshold: int = 100
     max_ratio: float = 0.8
     tag: int = 0
+    # levels with at most this many vertices train through the batched
+    # (single persistent launch) path instead of one launch per epoch; 0 = off
+    batch_levels_upto: int = 0
 
 
 @dataclass
@@ -57,7 +60,11 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
         if level_events:
             ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             ev[0].record(ctx.stream)
-        G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
+        if cfg.batch_levels_upto and sizes[i] <= cfg.batch_levels_upto:
+            G.gosh_train_batched(ctx, [(levels.csr(i), M, sched[i], cfg.lr, i, cfg.tag)], cfg.k,
+                                 G.GOSH_BATCH_AUTO, updates=counter)
+        else:
+            G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
         if level_events:
             ev[1].record(ctx.stream)
             events[i] = ev

@@ -125,3 +125,88 @@ def check_csr(offsets: np.ndarray, indices: np.ndarray) -> None:
     bwd = np.sort(indices.astype(np.int64) * n + src)
     if not np.array_equal(fwd, bwd):
         raise ValueError("not symmetric")
+
+
+# --------------------------------------------------------------------------- torch port
+def _s64(c: int) -> int:
+    """uint64 constant as the int64 with the same bits."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _lsr(z, k: int):
+    """Logical right shift of int64 tensors holding uint64 bit patterns."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def rmat_pairs_torch(scale: int, first: int, count: int, seed: int, device, abcd=RMAT_ABCD):
+    """The same draws as rmat_pairs, computed with torch int64 arithmetic
+    (wrapping multiplication has the uint64 bit pattern) on `device`."""
+    import torch
+    ta, tab, tabc = (int(x) for x in _thresholds(abcd))
+    idx = torch.arange(first, first + count, dtype=torch.int64, device=device)
+    base = (seed << 40) ^ (idx << 6)
+    row = torch.zeros(count, dtype=torch.int64, device=device)
+    col = torch.zeros(count, dtype=torch.int64, device=device)
+    gold, m1, m2 = _s64(0x9E3779B97F4A7C15), _s64(0xBF58476D1CE4E5B9), _s64(0x94D049BB133111EB)
+    for lvl in range(scale):
+        z = (base ^ lvl) + gold
+        z = (z ^ _lsr(z, 30)) * m1
+        z = (z ^ _lsr(z, 27)) * m2
+        z = z ^ _lsr(z, 31)
+        r = _lsr(z, 32)
+        bit = 1 << (scale - 1 - lvl)
+        row += (r >= tab).to(torch.int64) * bit
+        col += (((r >= ta) & (r < tab)) | (r >= tabc)).to(torch.int64) * bit
+    return row, col
+
+
+def rmat_csr_torch(scale: int, edge_factor: float, seed: int, device, n: int | None = None,
+                   abcd=RMAT_ABCD, chunk: int = 1 << 26, offsets_dtype=None):
+    """rmat_csr on `device`: returns torch (offsets, indices int32); offsets are
+    int64 unless offsets_dtype says otherwise.  Same graph as rmat_csr."""
+    import torch
+    if n is None:
+        n = 1 << scale
+    m = int(round(edge_factor * n))
+    keys = []
+    have = 0
+    first = 0
+    while have < m:
+        cnt = min(chunk, max(m - have, 1) * (1 if n == (1 << scale) else 2) + 1024)
+        r, c = rmat_pairs_torch(scale, first, cnt, seed, device, abcd)
+        first += cnt
+        if n != (1 << scale):
+            ok = (r < n) & (c < n)
+            r, c = r[ok], c[ok]
+        take = min(r.numel(), m - have)
+        r, c = r[:take], c[:take]
+        keep = r != c
+        r, c = r[keep], c[keep]
+        keys.append(torch.unique(torch.cat([r * n + c, c * n + r])))
+        have += take
+        del r, c
+    key = torch.unique(torch.cat(keys)) if keys else torch.zeros(0, dtype=torch.int64, device=device)
+    del keys
+    src = torch.div(key, n, rounding_mode="floor")
+    dst = (key - src * n).to(torch.int32)
+    del key
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offsets[1:] = torch.cumsum(torch.bincount(src, minlength=n), 0)
+    if offsets_dtype is not None:
+        offsets = offsets.to(offsets_dtype)
+    return offsets, dst
+
+
+def drop_isolated_torch(offsets, indices):
+    """Removes vertices without neighbours and relabels the rest in ascending
+    old id (torch tensors on any device).  Returns (offsets, indices, old_id)."""
+    import torch
+    deg = offsets[1:] - offsets[:-1]
+    keep = deg > 0
+    old_id = torch.nonzero(keep).flatten()
+    newid = torch.full((deg.numel(),), -1, dtype=torch.int64, device=offsets.device)
+    newid[old_id] = torch.arange(old_id.numel(), device=offsets.device)
+    new_off = torch.zeros(old_id.numel() + 1, dtype=offsets.dtype, device=offsets.device)
+    new_off[1:] = torch.cumsum(deg[keep], 0).to(offsets.dtype)
+    new_idx = newid[indices.long()].to(torch.int32)
+    return new_off, new_idx, old_id

@@ -90,3 +90,31 @@ def test_init_rows_range():
     M = init_rows(1000, 32, seed=3)
     assert M.dtype == np.float32 and M.shape == (1000, 32)
     assert np.abs(M).max() <= 0.5 / 32
+
+
+def test_torch_rmat_matches_numpy():
+    import torch
+    r0, c0 = rmat_pairs(13, 12345, 5000, seed=9)
+    r1, c1 = __import__("synth.rmat", fromlist=["rmat_pairs_torch"]).rmat_pairs_torch(13, 12345, 5000, 9, "cpu")
+    assert np.array_equal(r0, r1.numpy()) and np.array_equal(c0, c1.numpy())
+    from synth.rmat import rmat_csr_torch
+    for args in ((10, 8, 3, None), (11, 5.5, 4, 1500)):
+        off, idx = rmat_csr(args[0], args[1], seed=args[2], n=args[3])
+        to, ti = rmat_csr_torch(args[0], args[1], args[2], "cpu", n=args[3], chunk=3000)
+        assert np.array_equal(off, to.numpy()) and np.array_equal(idx, ti.numpy())
+
+
+def test_drop_isolated_torch():
+    import torch
+    from synth.rmat import drop_isolated_torch
+    off, idx = rmat_csr(10, 2, seed=4)
+    o, x, old = drop_isolated_torch(torch.from_numpy(off), torch.from_numpy(idx))
+    o, x, old = o.numpy(), x.numpy(), old.numpy()
+    check_csr(o, x)
+    assert np.all(np.diff(o) > 0)
+    # same edge set after mapping back to old ids
+    src = np.repeat(np.arange(len(o) - 1), np.diff(o))
+    n0 = len(off) - 1
+    a = np.sort(old[src] * n0 + old[x])
+    s0 = np.repeat(np.arange(n0), np.diff(off))
+    assert np.array_equal(a, np.sort(s0 * n0 + idx))
