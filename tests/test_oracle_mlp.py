@@ -1,0 +1,105 @@
+"""Pins of the learned-prolongation reference: GELU against its closed form
+and known values, backward against central finite differences of the MSE,
+the zero-output-layer case against copy prolongation, Adam's first step."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def test_gelu_known_values():
+    # x Phi(x): Phi(0) = 1/2, Phi(1) = 0.8413447460685429, Phi(-1) = 1 - Phi(1)
+    assert mlp.gelu(0.0) == 0.0
+    assert mlp.gelu(1.0) == pytest.approx(0.8413447460685429, rel=1e-15)
+    assert mlp.gelu(-1.0) == pytest.approx(-0.15865525393145707, rel=1e-14)
+    assert mlp.gelu(40.0) == pytest.approx(40.0)
+    assert abs(mlp.gelu(-40.0)) < 1e-300
+    assert mlp.gelu_grad(0.0) == pytest.approx(0.5)
+
+
+def test_gelu_grad_finite_differences():
+    z = np.linspace(-4, 4, 41)
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_grad(z), fd, rtol=1e-8, atol=1e-10)
+
+
+def _problem(seed, B=7, d=6, H=5):
+    rng = np.random.default_rng(seed)
+    C = rng.normal(size=(B, d)) * 0.3
+    X = mlp.features(C, rng.integers(0, 50, B), rng.integers(1, 20, B))
+    T = C + rng.normal(size=(B, d)) * 0.1
+    P = mlp.init_params(d, H, seed, w2_zero=False)
+    P.b1 = rng.normal(size=H) * 0.1
+    P.b2 = rng.normal(size=d) * 0.1
+    return P, X, C, T
+
+
+def test_backward_matches_finite_differences():
+    P, X, C, T = _problem(1)
+    Y, cache = mlp.forward(P, X, C)
+    g = mlp.backward(P, Y, T, cache)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2"):
+        W = getattr(P, name)
+        G = getattr(g, name)
+        it = np.nditer(W, flags=["multi_index"])
+        for _ in it:
+            i = it.multi_index
+            old = W[i]
+            W[i] = old + h
+            lp = mlp.mse(mlp.forward(P, X, C)[0], T)
+            W[i] = old - h
+            lm = mlp.mse(mlp.forward(P, X, C)[0], T)
+            W[i] = old
+            assert G[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-10), (name, i)
+
+
+def test_zero_output_layer_is_copy_prolongation():
+    P, X, C, T = _problem(2)
+    P.W2[...] = 0.0
+    P.b2[...] = 0.0
+    Y, _ = mlp.forward(P, X, C)
+    assert np.array_equal(Y, C)
+
+
+def test_features_layout():
+    C = np.arange(6.0).reshape(2, 3)
+    X = mlp.features(C, [0, 3], [1, 4])
+    assert np.array_equal(X[:, :3], C)
+    assert X[0, 3] == 0.0 and X[1, 3] == pytest.approx(math.log(4.0))
+    assert X[0, 4] == 0.0 and X[1, 4] == pytest.approx(math.log(4.0))
+
+
+def test_adam_first_step_is_signed_lr():
+    # with bias correction the first Adam step moves every weight by
+    # lr * g / (|g| + eps) -> lr * sign(g)
+    P, X, C, T = _problem(3)
+    Y, cache = mlp.forward(P, X, C)
+    g = mlp.backward(P, Y, T, cache)
+    Q = P.copy()
+    S = mlp.adam_init(Q)
+    mlp.adam_step(Q, g, S, 1e-3)
+    for name in ("W1", "W2"):
+        step = getattr(P, name) - getattr(Q, name)
+        G = getattr(g, name)
+        big = np.abs(G) > 1e-6
+        assert np.allclose(step[big], 1e-3 * np.sign(G[big]), rtol=1e-3)
+
+
+def test_training_reduces_mse():
+    rng = np.random.default_rng(4)
+    B, d, H = 256, 8, 16
+    C = rng.normal(size=(B, d)) * 0.3
+    deg = rng.integers(1, 30, B)
+    X = mlp.features(C, deg, rng.integers(1, 10, B))
+    T = C * 0.5 + 0.05 * np.log1p(deg)[:, None]     # learnable shift from the features
+    P = mlp.init_params(d, H, 4)
+    S = mlp.adam_init(P)
+    first = mlp.mse(mlp.forward(P, X, C)[0], T)
+    for _ in range(300):
+        Y, cache = mlp.forward(P, X, C)
+        mlp.adam_step(P, mlp.backward(P, Y, T, cache), S, 1e-2)
+    assert mlp.mse(mlp.forward(P, X, C)[0], T) < 0.1 * first
