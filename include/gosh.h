@@ -54,6 +54,7 @@ typedef enum { GOSH_F32 = 0, GOSH_BF16 = 1 } gosh_dtype;
 
 typedef struct gosh_ctx gosh_ctx;
 typedef struct gosh_levels gosh_levels;
+typedef struct gosh_mlp gosh_mlp;
 
 /* Borrowed device view of a CSR graph (see conventions). */
 typedef struct {
@@ -194,11 +195,84 @@ gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t
                                gosh_dtype dt, int32_t d, int32_t k, gosh_batch_mode mode,
                                uint64_t* updates_dev, int32_t* chosen_out);
 
-/* ExpandEmbedding (Algorithm 2): fine[v] = coarse[map_{fine_level}[v]] for
- * every vertex v of level fine_level.  coarse_emb: [n_{fine_level+1}, d],
- * fine_emb: [n_{fine_level}, d], both device, same dtype.  Asynchronous. */
+/* ExpandEmbedding (Algorithm 2): every vertex v of level fine_level starts
+ * from the trained row of its super vertex.  mlp == NULL: copy,
+ * fine[v] = coarse[map_{fine_level}[v]] (bit-exact).  Otherwise the learned
+ * prolongation (an addition, not in the paper): with c = coarse[map v],
+ * y = c + W2 GELU(W1 [c, log1p(deg v), log(clsz(map v))] + b1) + b2, where
+ * deg is v's degree in level fine_level and clsz the size of its cluster;
+ * products in BF16 with FP32 accumulation, c, the biases and the sum in
+ * FP32, BF16 rows rounded to nearest even.  W2 = 0, b2 = 0 reproduces the
+ * copy exactly.  coarse_emb: [n_{fine_level+1}, d], fine_emb:
+ * [n_{fine_level}, d], both device, same dtype, not overlapping; the
+ * network's d must equal d.  Asynchronous. */
 gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_level,
-                         const void* coarse_emb, void* fine_emb, gosh_dtype dt, int32_t d);
+                         const void* coarse_emb, void* fine_emb, gosh_dtype dt, int32_t d,
+                         const gosh_mlp* mlp);
+
+/* ---------------------------------------------------------------- learned prolongation */
+
+/* Creates the prolongation network for rows of width d (32, 64, 128 or 256)
+ * with `hidden` GELU units (64, 128 or 256).  The library owns its FP32
+ * master weights, Adam moments and BF16 operand copies (device memory
+ * charged to the context).  W1 is drawn uniformly from +-1/sqrt(d+2) with
+ * the context's Philox key, b1, W2 and b2 start at 0 (so the network starts
+ * as copy prolongation).  Destroy before or after the context (a network
+ * whose context is gone only accepts gosh_mlp_destroy). */
+gosh_status gosh_mlp_create(gosh_ctx* ctx, int32_t d, int32_t hidden, gosh_mlp** out);
+gosh_status gosh_mlp_destroy(gosh_mlp* mlp);
+/* Number of parameters P = hidden*(d+2) + hidden + d*hidden + d. */
+gosh_status gosh_mlp_num_params(const gosh_mlp* mlp, int64_t* n);
+/* Host FP32 parameter vector of P floats, in order W1 [hidden][d+2]
+ * (row-major; column d is log1p(deg), column d+1 is log(clsz)), b1 [hidden],
+ * W2 [d][hidden], b2 [d].  set also clears the Adam state.  Both
+ * synchronous. */
+gosh_status gosh_mlp_set_weights(gosh_ctx* ctx, gosh_mlp* mlp, const float* params_host);
+gosh_status gosh_mlp_get_weights(gosh_ctx* ctx, const gosh_mlp* mlp, float* params_host);
+
+/* An explicit batch of training rows (all device arrays of `rows` entries):
+ * coarse rows [rows, d], fine degrees, cluster sizes (>= 1) and target rows
+ * [rows, d]; rows of the call's dtype. */
+typedef struct {
+    int64_t rows;
+    const void* coarse;
+    const int32_t* deg;
+    const int32_t* clsz;
+    const void* target;
+} gosh_mlp_batch;
+
+/* Gradient of the mean squared error mean((y - target)^2) over all
+ * rows*d entries with respect to the parameters, written to grads_dev
+ * (device, P floats, parameter order as above); loss_dev (device float,
+ * may be NULL) receives the loss.  Products in BF16 with FP32 accumulation
+ * (inputs, hidden activations and output gradients rounded to BF16).
+ * 1 <= rows <= 2^24.  Synchronous. */
+gosh_status gosh_mlp_grad(gosh_ctx* ctx, gosh_mlp* mlp, gosh_dtype dt, const gosh_mlp_batch* batch,
+                          float* grads_dev, float* loss_dev);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
+ * FP32 master weights with the given gradient (device, P floats).
+ * Asynchronous. */
+gosh_status gosh_mlp_adam_step(gosh_ctx* ctx, gosh_mlp* mlp, const float* grads_dev, float lr);
+
+/* Training pairs: every vertex v of level `level` of lv (which must have a
+ * coarser level) with input coarse[map v] (trained rows of level+1) and
+ * target fine[v] (trained rows of level). */
+typedef struct {
+    const gosh_levels* lv;
+    int32_t level;
+    const void* coarse;
+    const void* fine;
+} gosh_mlp_source;
+
+/* `steps` Adam steps (learning rate lr) on minibatches of `batch` pairs drawn
+ * uniformly with replacement over the union of the sources' pairs (Philox
+ * with the context key; `tag` separates runs).  loss_dev (device, `steps`
+ * floats, may be NULL) receives each step's minibatch loss before its
+ * update.  Synchronous. */
+gosh_status gosh_mlp_train(gosh_ctx* ctx, gosh_mlp* mlp, gosh_dtype dt, const gosh_mlp_source* srcs_host,
+                           int32_t nsrc, int32_t steps, int32_t batch, float lr, uint32_t tag,
+                           float* loss_dev);
 
 /* ---------------------------------------------------------------- test hooks */
 

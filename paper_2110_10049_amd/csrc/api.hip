@@ -165,6 +165,10 @@ gosh_status gosh_ctx_destroy(gosh_ctx* ctx) {
         lv->owner = nullptr;
         lv->ctx = nullptr;
     }
+    for (gosh_mlp* m : ctx->mlps) {
+        m->owner = nullptr;
+        m->ctx = nullptr;
+    }
     for (auto& kv : c->live) (void)hipFree(kv.first);
     for (auto& kv : c->cache) (void)hipFree(kv.second);
     delete ctx;
@@ -404,14 +408,113 @@ gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t
 }
 
 gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_level, const void* coarse_emb,
-                         void* fine_emb, gosh_dtype dt, int32_t d) {
+                         void* fine_emb, gosh_dtype dt, int32_t d, const gosh_mlp* mlp) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     return guarded(ctx, [&] {
         const gosh::Level& L = level_of(lv, fine_level);
         GOSH_REQUIRE(fine_level + 1 < static_cast<int32_t>(lv->lv.size()), GOSH_E_INVALID_ARG,
                      "fine_level must have a coarser level");
         set_device(&ctx->c);
-        gosh::prolong_copy(&ctx->c, L, coarse_emb, fine_emb, dt, d);
+        if (mlp) {
+            GOSH_REQUIRE(mlp->owner == ctx, GOSH_E_INVALID_ARG, "network belongs to another context");
+            gosh::mlp_prolong(&ctx->c, mlp, L, lv->lv[fine_level + 1].n, coarse_emb, fine_emb, dt, d);
+        } else {
+            gosh::prolong_copy(&ctx->c, L, coarse_emb, fine_emb, dt, d);
+        }
+    });
+}
+
+namespace {
+gosh_mlp* mlp_of(gosh_ctx* ctx, const gosh_mlp* m) {
+    GOSH_REQUIRE(m, GOSH_E_INVALID_ARG, "null network");
+    GOSH_REQUIRE(m->owner == ctx, GOSH_E_INVALID_ARG, "network belongs to another context");
+    return const_cast<gosh_mlp*>(m);
+}
+}  // namespace
+
+gosh_status gosh_mlp_create(gosh_ctx* ctx, int32_t d, int32_t hidden, gosh_mlp** out) {
+    if (!ctx || !out) return GOSH_E_INVALID_ARG;
+    *out = nullptr;
+    return guarded(ctx, [&] {
+        set_device(&ctx->c);
+        gosh_mlp* m = gosh::mlp_create(ctx, d, hidden);
+        ctx->mlps.insert(m);
+        *out = m;
+    });
+}
+
+gosh_status gosh_mlp_destroy(gosh_mlp* mlp) {
+    if (!mlp) return GOSH_OK;
+    if (mlp->owner) {
+        (void)hipSetDevice(mlp->ctx->device);
+        (void)hipStreamSynchronize(mlp->ctx->stream);
+        gosh::mlp_free(mlp);
+        mlp->owner->mlps.erase(mlp);
+    }
+    delete mlp;
+    return GOSH_OK;
+}
+
+gosh_status gosh_mlp_num_params(const gosh_mlp* mlp, int64_t* n) {
+    if (!mlp || !n) return GOSH_E_INVALID_ARG;
+    *n = mlp->nparams;
+    return GOSH_OK;
+}
+
+gosh_status gosh_mlp_set_weights(gosh_ctx* ctx, gosh_mlp* mlp, const float* params_host) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        gosh_mlp* m = mlp_of(ctx, mlp);
+        set_device(&ctx->c);
+        gosh::mlp_set_weights(&ctx->c, m, params_host);
+    });
+}
+
+gosh_status gosh_mlp_get_weights(gosh_ctx* ctx, const gosh_mlp* mlp, float* params_host) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        gosh_mlp* m = mlp_of(ctx, mlp);
+        set_device(&ctx->c);
+        gosh::mlp_get_weights(&ctx->c, m, params_host);
+    });
+}
+
+gosh_status gosh_mlp_grad(gosh_ctx* ctx, gosh_mlp* mlp, gosh_dtype dt, const gosh_mlp_batch* batch,
+                          float* grads_dev, float* loss_dev) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        gosh_mlp* m = mlp_of(ctx, mlp);
+        set_device(&ctx->c);
+        gosh::mlp_grad(&ctx->c, m, dt, batch, grads_dev, loss_dev);
+    });
+}
+
+gosh_status gosh_mlp_adam_step(gosh_ctx* ctx, gosh_mlp* mlp, const float* grads_dev, float lr) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        gosh_mlp* m = mlp_of(ctx, mlp);
+        set_device(&ctx->c);
+        gosh::mlp_adam_step(&ctx->c, m, grads_dev, lr);
+    });
+}
+
+gosh_status gosh_mlp_train(gosh_ctx* ctx, gosh_mlp* mlp, gosh_dtype dt, const gosh_mlp_source* srcs_host,
+                           int32_t nsrc, int32_t steps, int32_t batch, float lr, uint32_t tag, float* loss_dev) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        gosh_mlp* m = mlp_of(ctx, mlp);
+        GOSH_REQUIRE(nsrc >= 1 && srcs_host, GOSH_E_INVALID_ARG, "no pair sources");
+        std::vector<gosh::PairSrcHost> v;
+        for (int32_t i = 0; i < nsrc; ++i) {
+            const gosh_mlp_source& s = srcs_host[i];
+            const gosh::Level& L = level_of(s.lv, s.level);
+            GOSH_REQUIRE(s.lv->owner == ctx, GOSH_E_INVALID_ARG, "levels belong to another context");
+            GOSH_REQUIRE(s.level + 1 < static_cast<int32_t>(s.lv->lv.size()), GOSH_E_INVALID_ARG,
+                         "source level must have a coarser level");
+            v.push_back(gosh::PairSrcHost{&L, s.lv->lv[s.level + 1].n, s.coarse, s.fine});
+        }
+        set_device(&ctx->c);
+        gosh::mlp_train(&ctx->c, m, dt, v, steps, batch, lr, tag, loss_dev);
     });
 }
 

@@ -100,10 +100,12 @@ struct Level {
 }  // namespace gosh
 
 struct gosh_levels;
+struct gosh_mlp;
 
 struct gosh_ctx {
     gosh::Ctx c;
     std::set<gosh_levels*> levels;   // live hierarchies built on this context
+    std::set<gosh_mlp*> mlps;        // live prolongation networks
 };
 
 struct gosh_levels {
@@ -112,7 +114,32 @@ struct gosh_levels {
     std::vector<gosh::Level> lv;
 };
 
+// Learned-prolongation network: FP32 master weights, Adam moments and the
+// BF16 operand fragments of the products (see mlp.hip).
+struct gosh_mlp {
+    gosh_ctx* owner = nullptr;       // cleared when the context is destroyed first
+    gosh::Ctx* ctx = nullptr;
+    int d = 0, hidden = 0;
+    int64_t nparams = 0;
+    float* master = nullptr;   // W1[H][d+2], b1[H], W2[d][H], b2[d]
+    float* m1 = nullptr;       // Adam first moments
+    float* m2 = nullptr;       // Adam second moments
+    int64_t t = 0;             // Adam steps taken
+    uint16_t* w1f = nullptr;   // BF16 fragments of W1 (layer-1 A operand)
+    uint16_t* w2f = nullptr;   // BF16 fragments of W2 (layer-2 A operand, permuted K)
+    uint16_t* w2tf = nullptr;  // BF16 fragments of W2^T (backward-data A operand)
+};
+
 namespace gosh {
+
+// One source of (coarse row, fine row) training pairs: every vertex of a
+// fine level with its super vertex in the next level.
+struct PairSrcHost {
+    const Level* L;
+    int64_t n_coarse;
+    const void* coarse;
+    const void* fine;
+};
 
 // ---------------------------------------------------------------- host entry points
 // (implemented in coarsen.hip / train.hip / prolong.hip)
@@ -132,5 +159,16 @@ void prolong_copy(Ctx* c, const Level& fine, const void* coarse, void* fine_emb,
 void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
                    uint64_t* updates_dev, int32_t* chosen);
 void free_level(Ctx* c, Level& L);
+// (mlp.hip)
+gosh_mlp* mlp_create(gosh_ctx* owner, int d, int hidden);
+void mlp_free(gosh_mlp* M);
+void mlp_set_weights(Ctx* c, gosh_mlp* M, const float* host);
+void mlp_get_weights(Ctx* c, const gosh_mlp* M, float* host);
+void mlp_prolong(Ctx* c, const gosh_mlp* M, const Level& fine, int64_t n_coarse, const void* coarse,
+                 void* fine_emb, gosh_dtype dt, int d);
+void mlp_grad(Ctx* c, gosh_mlp* M, gosh_dtype dt, const gosh_mlp_batch* b, float* grads, float* loss);
+void mlp_adam_step(Ctx* c, gosh_mlp* M, const float* grads, float lr);
+void mlp_train(Ctx* c, gosh_mlp* M, gosh_dtype dt, const std::vector<PairSrcHost>& srcs, int steps,
+               int batch, float lr, uint32_t tag, float* loss_dev);
 
 }  // namespace gosh

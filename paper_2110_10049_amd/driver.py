@@ -37,14 +37,20 @@ class EmbedResult:
     updates: int = 0
     levels: object = None
     timings: dict = field(default_factory=dict)
+    # trained rows of every level (level -> tensor), when asked for with keep_levels
+    trained: dict = field(default_factory=dict)
 
 
 def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels | None = None,
-          coarsen: bool = True, level_events: bool = False) -> EmbedResult:
+          coarsen: bool = True, level_events: bool = False, mlp: G.Mlp | None = None,
+          keep_levels: bool = False) -> EmbedResult:
     """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level.
 
     With level_events, timings["train_events"][i] holds a (start, end) pair
-    of events recorded on the context stream around level i's training."""
+    of events recorded on the context stream around level i's training.
+    mlp: expand with the learned prolongation instead of the copy.
+    keep_levels: keep every level's trained rows in result.trained (the
+    (coarse, fine) pairs the prolongation network is trained on)."""
     if levels is None:
         levels = G.gosh_coarsen(ctx, g0, cfg.threshold, cfg.max_ratio) if coarsen else G.gosh_levels_single(ctx, g0)
     D = levels.count()
@@ -56,6 +62,7 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
         raise ValueError("init_fn returned a wrong shape or dtype")
     counter = torch.zeros(1, dtype=torch.int64, device=dev)
     events = {}
+    trained = {}
     for i in range(D - 1, -1, -1):
         if level_events:
             ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -68,9 +75,11 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
         if level_events:
             ev[1].record(ctx.stream)
             events[i] = ev
+        if keep_levels:
+            trained[i] = M
         if i > 0:
             fine = torch.empty((sizes[i - 1], cfg.d), dtype=cfg.dtype, device=dev)
-            G.gosh_prolong(ctx, levels, i - 1, M, fine)
+            G.gosh_prolong(ctx, levels, i - 1, M, fine, mlp=mlp)
             M = fine
     return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels,
-                       timings={"train_events": events})
+                       timings={"train_events": events}, trained=trained)

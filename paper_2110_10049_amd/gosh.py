@@ -40,6 +40,15 @@ class gosh_job(C.Structure):
 GOSH_BATCH_AUTO, GOSH_BATCH_PERSISTENT, GOSH_BATCH_EPOCH_GRAPH = 0, 1, 2
 
 
+class gosh_mlp_batch(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("coarse", C.c_void_p), ("deg", C.c_void_p), ("clsz", C.c_void_p),
+                ("target", C.c_void_p)]
+
+
+class gosh_mlp_source(C.Structure):
+    _fields_ = [("lv", C.c_void_p), ("level", C.c_int32), ("coarse", C.c_void_p), ("fine", C.c_void_p)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -66,7 +75,16 @@ _SIGNATURES = [
                              C.c_int32, C.c_uint32, _P]),
     ("gosh_train_batched", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
                                      C.c_int, _P, C.POINTER(C.c_int32)]),
-    ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32]),
+    ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32, _P]),
+    ("gosh_mlp_create", C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    ("gosh_mlp_destroy", C.c_int, [_P]),
+    ("gosh_mlp_num_params", C.c_int, [_P, C.POINTER(C.c_int64)]),
+    ("gosh_mlp_set_weights", C.c_int, [_P, _P, _P]),
+    ("gosh_mlp_get_weights", C.c_int, [_P, _P, _P]),
+    ("gosh_mlp_grad", C.c_int, [_P, _P, C.c_int, C.POINTER(gosh_mlp_batch), _P, _P]),
+    ("gosh_mlp_adam_step", C.c_int, [_P, _P, _P, C.c_float]),
+    ("gosh_mlp_train", C.c_int, [_P, _P, C.c_int, C.POINTER(gosh_mlp_source), C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_float, C.c_uint32, _P]),
     ("gosh_draw_samples", C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P]),
     ("gosh_update_batch", C.c_int, [_P, _P, C.c_int, C.c_int32, C.c_int64, C.c_int32, _P, _P,
                                     C.c_int32, C.c_float, C.c_int32, C.c_uint32, C.c_int32]),
@@ -267,13 +285,101 @@ def gosh_train(ctx: Context, lv: Levels, level: int, emb: torch.Tensor, epochs: 
     ctx.check(lib().gosh_train(ctx.h, lv.h, level, e, _dtype_code(emb), emb.shape[1], epochs, lr, k, tag, u))
 
 
-def gosh_prolong(ctx: Context, lv: Levels, fine_level: int, coarse: torch.Tensor, fine: torch.Tensor):
+def gosh_prolong(ctx: Context, lv: Levels, fine_level: int, coarse: torch.Tensor, fine: torch.Tensor,
+                 mlp: "Mlp | None" = None):
     nf, _ = lv.shape(fine_level)
     nc, _ = lv.shape(fine_level + 1)
     if coarse.shape != (nc, fine.shape[1]) or fine.shape[0] != nf or coarse.dtype != fine.dtype:
         raise ValueError("prolong shapes/dtypes do not match the levels")
     ctx.check(lib().gosh_prolong(ctx.h, lv.h, fine_level, _dev(coarse, name="coarse"), _dev(fine, name="fine"),
-                                 _dtype_code(fine), fine.shape[1]))
+                                 _dtype_code(fine), fine.shape[1], mlp.h if mlp is not None else None))
+
+
+class Mlp:
+    """A gosh_mlp prolongation network (library-owned weights)."""
+
+    def __init__(self, ctx: Context, d: int, hidden: int):
+        self.ctx, self.d, self.hidden = ctx, d, hidden
+        h = C.c_void_p()
+        ctx.check(lib().gosh_mlp_create(ctx.h, d, hidden, C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        ctx.check(lib().gosh_mlp_num_params(self.h, C.byref(n)))
+        self.nparams = n.value
+
+    def split(self, flat):
+        """Views (W1 [H, d+2], b1 [H], W2 [d, H], b2 [d]) of a flat parameter vector."""
+        d, H = self.d, self.hidden
+        a = H * (d + 2)
+        return (flat[:a].reshape(H, d + 2), flat[a:a + H], flat[a + H:a + H + d * H].reshape(d, H),
+                flat[a + H + d * H:])
+
+    def set_weights(self, flat):
+        import numpy as np
+        w = np.ascontiguousarray(flat, dtype=np.float32).ravel()
+        if w.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters")
+        self.ctx.check(lib().gosh_mlp_set_weights(self.ctx.h, self.h, w.ctypes.data))
+
+    def get_weights(self):
+        import numpy as np
+        w = np.zeros(self.nparams, np.float32)
+        self.ctx.check(lib().gosh_mlp_get_weights(self.ctx.h, self.h, w.ctypes.data))
+        return w
+
+    def grad(self, coarse: torch.Tensor, deg: torch.Tensor, clsz: torch.Tensor, target: torch.Tensor):
+        """(gradient [P] float32 device tensor, loss float) of the MSE on an explicit batch."""
+        B = coarse.shape[0]
+        if coarse.shape != (B, self.d) or target.shape != coarse.shape or target.dtype != coarse.dtype:
+            raise ValueError("coarse and target must be [rows, d] of one dtype")
+        if deg.numel() != B or clsz.numel() != B:
+            raise ValueError("deg and clsz need one entry per row")
+        b = gosh_mlp_batch(B, _dev(coarse, name="coarse").value, _dev(deg, torch.int32, "deg").value,
+                           _dev(clsz, torch.int32, "clsz").value, _dev(target, name="target").value)
+        g = torch.empty(self.nparams, dtype=torch.float32, device=coarse.device)
+        loss = torch.empty(1, dtype=torch.float32, device=coarse.device)
+        self.ctx.check(lib().gosh_mlp_grad(self.ctx.h, self.h, _dtype_code(coarse), C.byref(b), _dev(g),
+                                           _dev(loss)))
+        return g, float(loss.item())
+
+    def adam_step(self, grads: torch.Tensor, lr: float):
+        if grads.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} gradients")
+        self.ctx.check(lib().gosh_mlp_adam_step(self.ctx.h, self.h, _dev(grads, torch.float32, "grads"), lr))
+
+    def train(self, sources, steps: int, batch: int, lr: float, tag: int = 0, losses: bool = True):
+        """sources: list of (Levels, level, coarse rows, fine rows).  Returns the
+        per-step minibatch losses (a float32 device tensor) or None."""
+        arr = (gosh_mlp_source * len(sources))()
+        dtype = None
+        for i, (lv, level, coarse, fine) in enumerate(sources):
+            dtype = coarse.dtype if dtype is None else dtype
+            if coarse.dtype != dtype or fine.dtype != dtype:
+                raise ValueError("all sources need one dtype")
+            nf, _ = lv.shape(level)
+            nc, _ = lv.shape(level + 1)
+            if coarse.shape != (nc, self.d) or fine.shape != (nf, self.d):
+                raise ValueError("source shapes do not match the levels")
+            arr[i] = gosh_mlp_source(lv.h.value, level, _dev(coarse, name="coarse").value,
+                                     _dev(fine, name="fine").value)
+        out = None
+        if losses and steps > 0:
+            out = torch.empty(steps, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        code = _dtype_code(sources[0][2]) if sources else GOSH_F32
+        self.ctx.check(lib().gosh_mlp_train(self.ctx.h, self.h, code, arr, len(sources), steps, batch, lr, tag,
+                                            _dev(out) if out is not None else None))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().gosh_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gosh_draw_samples(ctx: Context, lv: Levels, level: int, epoch: int, k: int, tag: int = 0) -> torch.Tensor:

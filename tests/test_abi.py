@@ -54,3 +54,14 @@ def test_null_context_is_rejected():
     assert L.gosh_train(None, None, 0, None, 0, 128, 1, 0.1, 3, 0, None) == 1
     assert L.gosh_last_error(None) == b"null context"
     assert L.gosh_ctx_destroy(None) == 0
+
+
+def test_mlp_entry_points_reject_null():
+    from paper_2110_10049_amd import gosh as G
+    L = G.lib()
+    n = C.c_int64()
+    assert L.gosh_mlp_num_params(None, C.byref(n)) == 1
+    assert L.gosh_mlp_destroy(None) == 0
+    assert L.gosh_mlp_create(None, 128, 256, C.byref(C.c_void_p())) == 1
+    assert L.gosh_mlp_train(None, None, 0, None, 0, 1, 32, 0.1, 0, None) == 1
+    assert L.gosh_prolong(None, None, 0, None, None, 0, 128, None) == 1
