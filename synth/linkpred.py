@@ -87,13 +87,18 @@ def _draw_negatives(n, count, forbidden_keys, rng):
     return out
 
 
-def evaluate_auc(emb: np.ndarray, split: LinkSplit, seed: int,
-                 max_train: int = 2_000_000, max_test: int | None = None) -> float:
-    """AUCROC of a logistic-regression link predictor on Hadamard features."""
-    from sklearn.linear_model import LogisticRegression
-    from sklearn.metrics import roc_auc_score
+@dataclass
+class EvalPairs:
+    xtr: np.ndarray     # [N, 2] classifier training pairs
+    ytr: np.ndarray
+    xte: np.ndarray     # [M, 2] test pairs
+    yte: np.ndarray
 
-    emb = np.asarray(emb, dtype=np.float64)
+
+def make_eval_pairs(split: LinkSplit, seed: int, max_train: int = 2_000_000,
+                    max_test: int | None = None) -> EvalPairs:
+    """The labelled pairs evaluate_auc scores (same draws for the same seed),
+    built once so that several embeddings of one split can share them."""
     n = split.n
     rng = np.random.default_rng(seed)
     tr_keys = np.sort(split.train_pos[:, 0] * n + split.train_pos[:, 1])
@@ -112,8 +117,23 @@ def evaluate_auc(emb: np.ndarray, split: LinkSplit, seed: int,
     if max_test is not None and len(xte) > max_test:
         sel = rng.choice(len(xte), size=max_test, replace=False)
         xte, yte = xte[sel], yte[sel]
-    ftr = emb[xtr[:, 0]] * emb[xtr[:, 1]]
-    fte = emb[xte[:, 0]] * emb[xte[:, 1]]
+    return EvalPairs(xtr, ytr, xte, yte)
+
+
+def auc_on_pairs(emb: np.ndarray, P: EvalPairs) -> float:
+    """AUCROC of a logistic-regression link predictor on Hadamard features."""
+    from sklearn.linear_model import LogisticRegression
+    from sklearn.metrics import roc_auc_score
+
+    emb = np.asarray(emb, dtype=np.float64)
+    ftr = emb[P.xtr[:, 0]] * emb[P.xtr[:, 1]]
+    fte = emb[P.xte[:, 0]] * emb[P.xte[:, 1]]
     clf = LogisticRegression(max_iter=1000)
-    clf.fit(ftr, ytr)
-    return float(roc_auc_score(yte, clf.decision_function(fte)))
+    clf.fit(ftr, P.ytr)
+    return float(roc_auc_score(P.yte, clf.decision_function(fte)))
+
+
+def evaluate_auc(emb: np.ndarray, split: LinkSplit, seed: int,
+                 max_train: int = 2_000_000, max_test: int | None = None) -> float:
+    """AUCROC of a logistic-regression link predictor on Hadamard features."""
+    return auc_on_pairs(emb, make_eval_pairs(split, seed, max_train, max_test))

@@ -268,3 +268,34 @@ def test_mlp_argument_errors(gctx):
     with pytest.raises(G.GoshError):
         net.adam_step(torch.zeros(net.nparams, device="cuda"), float("nan"))
     assert last >= 1
+
+
+def test_prolong_full_size_sampled_rows(gctx, orc):
+    # level 0 -> 1 of the scale-22 R-MAT graph (edge factor 16, isolated
+    # vertices removed), d = 128, 256 hidden units, BF16 rows: the launch the
+    # benchmark times; 4096 sampled rows against the reference
+    from paper_2110_10049_amd import gosh as G
+    from synth.rmat import drop_isolated_torch, rmat_csr_torch
+    print("[mlp full size] scale 22", flush=True)
+    off, idx = rmat_csr_torch(22, 16, 1, "cuda")
+    off, idx, _ = drop_isolated_torch(off, idx)
+    g = G.CSR(off.contiguous(), idx.contiguous())
+    lv = G.gosh_coarsen(gctx, g, 100)
+    d, H = 128, 256
+    net = G.Mlp(gctx, d, H)
+    flat = _random_weights(d, H, 21)
+    net.set_weights(flat)
+    n0, _ = lv.shape(0)
+    n1, _ = lv.shape(1)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    coarse = (torch.randn((n1, d), generator=gen) * 0.3).to(torch.bfloat16).cuda()
+    fine = torch.empty((n0, d), device="cuda", dtype=torch.bfloat16)
+    G.gosh_prolong(gctx, lv, 0, coarse, fine, mlp=net)
+    torch.cuda.synchronize()
+    o, _, mp = lv.copy_out(0)
+    cs = lv.cluster_sizes(0)
+    rows = np.random.default_rng(8).choice(n0, 4096, replace=False)
+    rows = np.concatenate([rows, [0, n0 - 1]])
+    C = _rows(coarse)[mp[rows]]
+    Y, scale, ferr = _reference(orc, flat, d, H, C, (o[rows + 1] - o[rows]), cs[mp[rows]], C)
+    _check_close(_rows(fine[torch.from_numpy(rows).cuda()]), Y, scale, ferr, True)
