@@ -57,17 +57,35 @@ struct Shape {
 };
 
 // ------------------------------------------------------------ scalar helpers
-__device__ __forceinline__ uint32_t f2bf(float x) {   // round to nearest even; NaN stays quiet NaN
-    const uint32_t u = __float_as_uint(x);
-    if ((u & 0x7F800000u) == 0x7F800000u) return (u >> 16) | ((u & 0x007FFFFFu) ? 0x40u : 0u);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return f2bf(lo) | (f2bf(hi) << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * kRsqrt2)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * kRsqrt2)) + z * __expf(-0.5f * z * z) * kRsqrt2Pi;
+// FP32 -> BF16, round to nearest even (one v_cvt_pk_bf16_f32 per pair)
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    bf16x2 v;
+    v[0] = static_cast<__bf16>(lo);
+    v[1] = static_cast<__bf16>(hi);
+    return __builtin_bit_cast(uint32_t, v);
 }
+__device__ __forceinline__ uint32_t f2bf(float x) { return pack2(x, 0.0f) & 0xFFFFu; }
+
+// Lower tail Phi(-|z|) = erfc(|z| / sqrt 2) / 2 from the complementary error
+// function of Abramowitz and Stegun, Handbook of Mathematical Functions,
+// 7.1.26 (absolute error of erf at most 1.5e-7): for x >= 0,
+// erfc(x) ~= t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x),
+// here with x = |z| / sqrt 2 and the factor 1/2 folded into the a_i.  Also
+// returns exp(-z^2 / 2), which the derivative of GELU reuses.
+__device__ __forceinline__ float phi_lower(float z, float& ez) {
+    constexpr float kP = 0.3275911f * kRsqrt2;
+    constexpr float c1 = 0.5f * 0.254829592f, c2 = 0.5f * -0.284496736f, c3 = 0.5f * 1.421413741f,
+                    c4 = 0.5f * -1.453152027f, c5 = 0.5f * 1.061405429f;
+    constexpr float kNegHalfLog2e = -0.72134752044448170f;   // -log2(e) / 2
+    const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(z), kP, 1.0f));
+    const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, c5, c4), c3), c2), c1);
+    ez = __builtin_amdgcn_exp2f((z * z) * kNegHalfLog2e);
+    return poly * ez;
+}
+// GELU(z) = z Phi(z) (Hendrycks and Gimpel); GELU'(z) = Phi(z) + z exp(-z^2/2) / sqrt(2 pi).
 
 __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -171,8 +189,8 @@ __device__ __forceinline__ void load_x(const RowSrc& S, int64_t base, int lane, 
 }
 
 // One 32-wide hidden block: layer 1 for hidden rows 32 kb2 .. +31 and the
-// GELU, returned as layer-2 B fragments hb[nt] (permuted K order).  z and
-// gelu'(z) are handed to `keep` for the backward pass when it needs them.
+// GELU, returned as layer-2 B fragments hb[nt] (permuted K order).  z,
+// Phi(-|z|) and exp(-z^2/2) are handed to `keep` for the backward pass.
 template <int D, int H, int NT, class WPtr, class Keep>
 __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ b1, int kb2, int lane,
                                              const u32x4 (&xf)[NT][D / 32 + 1], u32x4 (&hb)[NT], Keep&& keep) {
@@ -202,8 +220,11 @@ __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ 
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float z = a1[m][nt][i] + bb[i];
-                g[i] = gelu(z);
-                keep(nt, h0 + i, z);
+                float ez;
+                const float lo = phi_lower(z, ez);        // Phi(-|z|)
+                const float zl = z * lo;
+                g[i] = z >= 0.0f ? z - zl : zl;            // z Phi(z)
+                keep(nt, h0 + i, z, lo, ez);
             }
             hb[nt][2 * m] = pack2(g[0], g[1]);
             hb[nt][2 * m + 1] = pack2(g[2], g[3]);
@@ -221,26 +242,38 @@ __global__ __launch_bounds__(kFwdThreads) void k_forward(RowSrc S, const u32x4* 
                                                          const float* __restrict__ b2, void* __restrict__ out,
                                                          int64_t ntiles) {
     constexpr int KB1 = D / 32 + 1, KB2 = H / 32, MT1 = H / 16, MT2 = D / 16;
-    constexpr int NF1 = MT1 * KB1 * 64, NF2 = MT2 * KB2 * 64;
-    __shared__ u32x4 lds[WLDS ? NF1 + NF2 : 1];
+    constexpr int NF1 = MT1 * KB1 * 64, NF2 = MT2 * KB2 * 64, NB = (H + D) / 4;
+    __shared__ u32x4 lds[WLDS ? NF1 + NF2 + NB : 1];
     const u32x4* w1 = W1f;
     const u32x4* w2 = W2f;
+    const float* bias1 = b1;
+    const float* bias2 = b2;
     if constexpr (WLDS) {
         for (int i = threadIdx.x; i < NF1; i += blockDim.x) lds[i] = W1f[i];
         for (int i = threadIdx.x; i < NF2; i += blockDim.x) lds[NF1 + i] = W2f[i];
+        float* lb = reinterpret_cast<float*>(lds + NF1 + NF2);
+        for (int i = threadIdx.x; i < H + D; i += blockDim.x) lb[i] = i < H ? b1[i] : b2[i - H];
         __syncthreads();
         w1 = lds;
         w2 = lds + NF1;
+        bias1 = lb;
+        bias2 = lb + H;
     }
     const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
     const int nw = blockDim.x >> 6;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * nw + (threadIdx.x >> 6); t < ntiles;
-         t += static_cast<int64_t>(gridDim.x) * nw) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * nw;
+    int64_t t = static_cast<int64_t>(blockIdx.x) * nw + (threadIdx.x >> 6);
+    // the gather of a tile's X is issued one tile ahead
+    u32x4 xf[NT][KB1];
+    int64_t cid[NT];
+    bool ok[NT];
+    if (t < ntiles) load_x<D, NT, BF16>(S, t * (16 * NT), lane, xf, cid, ok);
+    for (; t < ntiles; t += stride) {
         const int64_t base = t * (16 * NT);
-        u32x4 xf[NT][KB1];
-        int64_t cid[NT];
-        bool ok[NT];
-        load_x<D, NT, BF16>(S, base, lane, xf, cid, ok);
+        u32x4 xn[NT][KB1];
+        int64_t cn[NT];
+        bool okn[NT];
+        if (t + stride < ntiles) load_x<D, NT, BF16>(S, (t + stride) * (16 * NT), lane, xn, cn, okn);
         f32x4 acc[MT2][NT];
 #pragma unroll
         for (int mt = 0; mt < MT2; ++mt)
@@ -249,7 +282,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_forward(RowSrc S, const u32x4* 
 #pragma unroll 1
         for (int kb2 = 0; kb2 < KB2; ++kb2) {
             u32x4 hb[NT];
-            hidden_block<D, H, NT>(w1, b1, kb2, lane, xf, hb, [](int, int, float) {});
+            hidden_block<D, H, NT>(w1, bias1, kb2, lane, xf, hb, [](int, int, float, float, float) {});
 #pragma unroll
             for (int mt = 0; mt < MT2; ++mt) {
                 const u32x4 w = w2[(mt * KB2 + kb2) * 64 + lane];
@@ -265,12 +298,19 @@ __global__ __launch_bounds__(kFwdThreads) void k_forward(RowSrc S, const u32x4* 
             for (int mt = 0; mt < MT2; ++mt) {
                 const int f0 = mt * 16 + 4 * q;
                 const f32x4 c = load_row4<BF16>(S.coarse, cid[nt], D, f0);
-                const f32x4 bb = *reinterpret_cast<const f32x4*>(b2 + f0);
+                const f32x4 bb = *reinterpret_cast<const f32x4*>(bias2 + f0);
                 f32x4 y;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) y[i] = c[i] + (acc[mt][nt][i] + bb[i]);
                 store_row4<BF16>(out, r, D, f0, y);
             }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            cid[nt] = cn[nt];
+            ok[nt] = okn[nt];
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb) xf[nt][kb] = xn[nt][kb];
         }
     }
 }
@@ -330,8 +370,9 @@ __global__ __launch_bounds__(kTrainThreads) void k_train_fwd(RowSrc S, const voi
 #pragma unroll 1
     for (int kb2 = 0; kb2 < KB2; ++kb2) {
         u32x4 hb[NT];
-        hidden_block<D, H, NT>(W1f, b1, kb2, lane, xf, hb, [&](int nt, int h, float z) {
-            T.gp[static_cast<int64_t>(h) * bp + base + nt * 16 + r16] = gelu_grad(z);
+        hidden_block<D, H, NT>(W1f, b1, kb2, lane, xf, hb, [&](int nt, int h, float z, float lo, float ez) {
+            const float P = z >= 0.0f ? 1.0f - lo : lo;
+            T.gp[static_cast<int64_t>(h) * bp + base + nt * 16 + r16] = fmaf(z * ez, kRsqrt2Pi, P);   // GELU'(z)
         });
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -622,8 +663,8 @@ bool supported(int d, int h) {
 }
 
 template <int D, int H>
-constexpr bool fits_lds() {
-    return (H / 16) * (D / 32 + 1) + (D / 16) * (H / 32) <= kLdsLimitFrags;
+constexpr bool fits_lds() {   // weight fragments plus the biases (under one fragment)
+    return (H / 16) * (D / 32 + 1) + (D / 16) * (H / 32) + 1 <= kLdsLimitFrags;
 }
 
 int num_cus(int device) {
