@@ -71,6 +71,17 @@ def lib():
         L.orc_coarse_graph.restype = C.c_int64
         L.orc_epoch_schedule.argtypes = [C.c_int32, C.c_double, C.c_int32, _i32p]
         L.orc_epoch_schedule.restype = C.c_int32
+        L.orc_part_starts.argtypes = [C.c_int64, C.c_int32, _i64p]
+        L.orc_inside_out.argtypes = [C.c_int32, _i32p]
+        L.orc_inside_out.restype = C.c_int64
+        L.orc_pool.argtypes = [_i64p, _i32p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_void_p, C.c_void_p,
+                               C.c_void_p]
+        L.orc_pool.restype = C.c_int64
+        L.orc_train_partitioned.argtypes = [_i64p, _i32p, C.c_int64, C.POINTER(_Emb), C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_double, C.c_int32, C.c_uint64, C.c_int32,
+                                            C.c_uint32, C.POINTER(C.c_int64)]
+        L.orc_train_partitioned.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -263,3 +274,45 @@ def gosh_embed(offsets, indices, init_fn, d, e, p, lr, k, seed, threshold=100,
             M = prolong(M, maps[i - 1])
     return M, {"levels": D, "schedule": sched, "sizes": [len(g[0]) - 1 for g in graphs],
                "updates": updates[::-1]}
+
+
+# --------------------------------------------------------------------------- partitioned embedding
+def part_starts(n: int, K: int) -> np.ndarray:
+    out = np.zeros(K + 1, np.int64)
+    lib().orc_part_starts(n, K, out)
+    return out
+
+
+def inside_out(K: int) -> list:
+    buf = np.zeros(K * (K + 1), np.int32)
+    m = lib().orc_inside_out(K, buf)
+    return [(int(buf[2 * j]), int(buf[2 * j + 1])) for j in range(m)]
+
+
+def pool(offsets, indices, K, i, j, B, seed, level=0, tag=0, round=0):
+    """Entries (src, pos, b) of pool S_{i,j} of a round, in pool order."""
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    L = lib()
+    cnt = L.orc_pool(offsets, indices, n, K, i, j, B, seed, level, tag, round, None, None, None)
+    src = np.zeros(max(cnt, 1), np.int32)
+    pos = np.zeros(max(cnt, 1), np.int32)
+    bb = np.zeros(max(cnt, 1), np.int32)
+    L.orc_pool(offsets, indices, n, K, i, j, B, seed, level, tag, round, src.ctypes.data, pos.ctypes.data,
+               bb.ctypes.data)
+    return src[:cnt], pos[:cnt], bb[:cnt]
+
+
+def train_partitioned(offsets, indices, M, K, B, epochs, lr, k, seed, level=0, tag=0):
+    """Sequential Section-5 training in place on M; returns (updates, positives)."""
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    if M.shape[0] != n:
+        raise ValueError("embedding rows != |V|")
+    if not 0 <= k <= 15:
+        raise ValueError("k out of range")
+    e = _emb(M)
+    pos = C.c_int64()
+    upd = lib().orc_train_partitioned(offsets, indices, n, C.byref(e), K, B, epochs, lr, k, seed, level, tag,
+                                      C.byref(pos))
+    return int(upd), int(pos.value)

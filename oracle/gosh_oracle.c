@@ -178,8 +178,24 @@ static double row_get(const orc_emb* M, int64_t v, int32_t e)
     return ((const double*)M->rows)[v * M->d + e];
 }
 
-int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
-                  double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch)
+/* Stochastic-rounding bits as orc_sr_bits, with `hi` in bits 8.. of the
+ * counter's block field (0 for Algorithm 3; the opposite part of a
+ * partitioned visit). */
+static uint32_t sr_bits_hi(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                           int64_t src, uint32_t slot, int32_t e, int32_t d, uint32_t hi)
+{
+    const int32_t L = d >= 8 ? d / 8 : 1;
+    const int32_t w = e / 2;
+    uint32_t out[4];
+    orc_stream_block(seed, level, tag, epoch, src, 1u, slot, (hi << 8) | (uint32_t)(w % L), out);
+    const int32_t h = 2 * (w / L) + (e % 2);
+    const uint32_t word = out[h / 2];
+    return (h & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
+
+static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                        double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                        uint32_t hi)
 {
     const int32_t d = M->d;
     double* s = (double*)malloc(sizeof(double) * (size_t)d);
@@ -203,7 +219,7 @@ int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
         for (int32_t e = 0; e < d; ++e) {
             double val = m[e] + s[e] * score;
             if (M->bf16) {
-                uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, (uint32_t)t, e, d);
+                uint32_t r = sr_bits_hi(seed, level, tag, epoch, src, (uint32_t)t, e, d, hi);
                 ((uint16_t*)M->rows)[u * d + e] = orc_bf16_sr((float)val, r);
             } else {
                 ((double*)M->rows)[u * d + e] = val;
@@ -213,7 +229,7 @@ int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
     }
     for (int32_t e = 0; e < d; ++e) {
         if (M->bf16) {
-            uint32_t r = orc_sr_bits(seed, level, tag, epoch, src, 0xFFu, e, d);
+            uint32_t r = sr_bits_hi(seed, level, tag, epoch, src, 0xFFu, e, d, hi);
             ((uint16_t*)M->rows)[src * d + e] = orc_bf16_sr((float)s[e], r);
         } else {
             ((double*)M->rows)[src * d + e] = s[e];
@@ -222,6 +238,12 @@ int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
     free(s);
     free(m);
     return done;
+}
+
+int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                  double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch)
+{
+    return visit_hi(M, src, samples, k, lr, seed, level, tag, epoch, 0u);
 }
 
 int64_t orc_update_batch(orc_emb* M, int64_t nsrc, const int32_t* src,
@@ -380,4 +402,153 @@ int32_t orc_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out)
     }
     free(real);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Embedding with the matrix split into K parts (Section 5)                 */
+/* ------------------------------------------------------------------------ */
+void orc_part_starts(int64_t n, int32_t K, int64_t* starts)
+{
+    for (int32_t p = 0; p <= K; ++p)
+        starts[p] = (int64_t)(((__int128)p * n) / K);
+}
+
+int64_t orc_inside_out(int32_t K, int32_t* pairs)
+{
+    /* (0,0) first; from (a,b): (a, b+1) while a > b, else (a+1, 0). */
+    const int64_t len = (int64_t)K * (K + 1) / 2;
+    int32_t a = 0, b = 0;
+    for (int64_t j = 0; j < len; ++j) {
+        if (j > 0) {
+            if (a > b) {
+                b += 1;
+            } else {
+                a += 1;
+                b = 0;
+            }
+        }
+        pairs[2 * j] = a;
+        pairs[2 * j + 1] = b;
+    }
+    return len;
+}
+
+/* First position in the sorted row of u whose neighbour is >= x. */
+static int64_t row_lower(const int64_t* offsets, const int32_t* indices, int64_t u, int64_t x)
+{
+    int64_t lo = offsets[u], hi = offsets[u + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (indices[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+/* Neighbours of u inside part o: positions [*lo, *lo + return value). */
+static int64_t part_neighbours(const int64_t* offsets, const int32_t* indices, const int64_t* starts,
+                               int64_t u, int32_t o, int64_t* lo)
+{
+    *lo = row_lower(offsets, indices, u, starts[o]);
+    return row_lower(offsets, indices, u, starts[o + 1]) - *lo;
+}
+
+/* Positive of the b-th visit of u towards part o in round `round`: word 0 of
+ * block 0 of the stream at epoch round*B + b with the part in the slot field
+ * (c = neighbours of u in part o, > 0). */
+static int32_t part_positive(const int32_t* indices, int64_t lo, int64_t c, uint64_t seed, int32_t level,
+                             uint32_t tag, int32_t eps, int64_t u, int32_t o)
+{
+    uint32_t w[4];
+    orc_stream_block(seed, level, tag, eps, u, 0u, (uint32_t)o, 0u, w);
+    return indices[lo + scale_word(w[0], c)];
+}
+
+static int64_t pool_side(const int64_t* offsets, const int32_t* indices, const int64_t* starts,
+                         int32_t s, int32_t o, int32_t B, uint64_t seed, int32_t level, uint32_t tag,
+                         int32_t round, int32_t* src, int32_t* pos, int32_t* bb, int64_t at)
+{
+    for (int64_t u = starts[s]; u < starts[s + 1]; ++u) {
+        int64_t lo;
+        const int64_t c = part_neighbours(offsets, indices, starts, u, o, &lo);
+        if (c == 0)
+            continue;
+        for (int32_t b = 0; b < B; ++b) {
+            if (src) {
+                src[at] = (int32_t)u;
+                pos[at] = part_positive(indices, lo, c, seed, level, tag, round * B + b, u, o);
+                bb[at] = b;
+            }
+            ++at;
+        }
+    }
+    return at;
+}
+
+int64_t orc_pool(const int64_t* offsets, const int32_t* indices, int64_t n, int32_t K,
+                 int32_t i, int32_t j, int32_t B, uint64_t seed, int32_t level, uint32_t tag,
+                 int32_t round, int32_t* src_out, int32_t* pos_out, int32_t* b_out)
+{
+    int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(K + 1));
+    orc_part_starts(n, K, starts);
+    int64_t at = pool_side(offsets, indices, starts, i, j, B, seed, level, tag, round,
+                           src_out, pos_out, b_out, 0);
+    if (i != j)
+        at = pool_side(offsets, indices, starts, j, i, B, seed, level, tag, round,
+                       src_out, pos_out, b_out, at);
+    free(starts);
+    return at;
+}
+
+int64_t orc_train_partitioned(const int64_t* offsets, const int32_t* indices, int64_t n,
+                              orc_emb* M, int32_t K, int32_t B, int32_t epochs, double lr,
+                              int32_t k, uint64_t seed, int32_t level, uint32_t tag,
+                              int64_t* positives_out)
+{
+    int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(K + 1));
+    int32_t* pairs = (int32_t*)malloc(sizeof(int32_t) * (size_t)K * (size_t)(K + 1));
+    orc_part_starts(n, K, starts);
+    const int64_t npairs = orc_inside_out(K, pairs);
+    const int32_t rounds = (epochs + B - 1) / B;
+    const int64_t cap = (int64_t)epochs * n;      /* positive samples of `epochs` passes */
+    int64_t positives = 0, updates = 0;
+    int32_t samples[64];
+    uint32_t w[64];
+    for (int32_t rho = 0; rho < rounds; ++rho) {
+        const double f = 1.0 - (double)rho / (double)rounds;
+        const double lrr = lr * (f > 1e-4 ? f : 1e-4);
+        for (int64_t q = 0; q < npairs; ++q) {
+            const int32_t a = pairs[2 * q], b2 = pairs[2 * q + 1];
+            for (int32_t side = 0; side < (a != b2 ? 2 : 1); ++side) {
+                const int32_t s = side == 0 ? a : b2, o = side == 0 ? b2 : a;
+                const int64_t size_o = starts[o + 1] - starts[o];
+                for (int64_t u = starts[s]; u < starts[s + 1]; ++u) {
+                    int64_t lo;
+                    const int64_t c = part_neighbours(offsets, indices, starts, u, o, &lo);
+                    if (c == 0)
+                        continue;
+                    for (int32_t b = 0; b < B; ++b) {
+                        if (positives >= cap)
+                            continue;
+                        ++positives;
+                        const int32_t eps = rho * B + b;
+                        for (int32_t blk = 0; 4 * blk <= k; ++blk)
+                            orc_stream_block(seed, level, tag, eps, u, 0u, (uint32_t)o, (uint32_t)blk,
+                                             w + 4 * blk);
+                        samples[0] = indices[lo + scale_word(w[0], c)];
+                        for (int32_t t = 1; t <= k; ++t)
+                            samples[t] = (int32_t)(starts[o] + scale_word(w[t], size_o));
+                        updates += visit_hi(M, u, samples, k, lrr, seed, level, tag, eps, (uint32_t)o);
+                    }
+                }
+            }
+        }
+    }
+    if (positives_out)
+        *positives_out = positives;
+    free(starts);
+    free(pairs);
+    return updates;
 }

@@ -12,6 +12,7 @@
  *   - TrainInGPU ........... Algorithm 3 (Section 3.1), lr decay (Section 3)
  *   - MultiEdgeCollapse .... Algorithm 4 (Section 4), CSR build (Section 4.1)
  *   - epoch distribution ... Section 3 (calculateEpochs of Algorithm 2)
+ *   - partitioned embedding  Section 5 (parts, inside-out order, sample pools)
  * Philox4x32-10 follows Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers:
  * As Easy as 1, 2, 3", SC'11.
  */
@@ -98,6 +99,35 @@ int64_t orc_coarse_graph(const int64_t* offsets, const int32_t* indices, int64_t
 
 /* Epoch distribution over D levels (Section 3): e_out[i], i = 0 finest. */
 int32_t orc_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
+
+/* ---- Embedding with the matrix split into K parts (Section 5) ----------
+ * Part p holds the ids [starts[p], starts[p+1]), starts[p] = floor(p n / K).
+ * Kernel pairs follow the inside-out order: (0,0), then from (a,b) the next
+ * pair is (a, b+1) while a > b and (a+1, 0) once a = b; K(K+1)/2 pairs.
+ * Pool S_{i,j} of round r: for every u in part i with c > 0 neighbours in
+ * part j, B entries (u, pos, b), b = 0..B-1; then (if i != j) the same for
+ * every v in part j towards part i.  The positive of entry b is neighbour
+ * floor(w c / 2^32) of u's neighbours in the opposite part o (in row order),
+ * w = word 0 of the stream block at epoch r*B + b, kind 0, slot o, block 0.
+ * A visit's k negatives are words 1..k of the same stream, mapped onto
+ * part o; its stochastic-rounding bits carry o in bits 8.. of the block
+ * field.  With K = 1 and B = 1 this is Algorithm 3 exactly. */
+void    orc_part_starts(int64_t n, int32_t K, int64_t* starts);
+/* pairs[2j], pairs[2j+1] = (a_j, b_j); returns K(K+1)/2. */
+int64_t orc_inside_out(int32_t K, int32_t* pairs);
+/* Entries of pool S_{i,j} (arrays may be NULL to count only). */
+int64_t orc_pool(const int64_t* offsets, const int32_t* indices, int64_t n, int32_t K,
+                 int32_t i, int32_t j, int32_t B, uint64_t seed, int32_t level, uint32_t tag,
+                 int32_t round, int32_t* src_out, int32_t* pos_out, int32_t* b_out);
+/* ceil(epochs / B) rounds over all pairs in inside-out order, every pool
+ * entry visited in pool order with lr * max(1 - round/rounds, 1e-4); at most
+ * epochs * n positive visits run (later entries are skipped).  Returns the
+ * executed UpdateEmbed calls; *positives_out (may be NULL) the positive
+ * visits. */
+int64_t orc_train_partitioned(const int64_t* offsets, const int32_t* indices, int64_t n,
+                              orc_emb* M, int32_t K, int32_t B, int32_t epochs, double lr,
+                              int32_t k, uint64_t seed, int32_t level, uint32_t tag,
+                              int64_t* positives_out);
 
 #ifdef __cplusplus
 }
