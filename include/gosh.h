@@ -210,6 +210,81 @@ gosh_status gosh_prolong(gosh_ctx* ctx, const gosh_levels* lv, int32_t fine_leve
                          const void* coarse_emb, void* fine_emb, gosh_dtype dt, int32_t d,
                          const gosh_mlp* mlp);
 
+/* ---------------------------------------------------------------- partitioned embedding */
+
+/* Parameters of the partitioned embedding of Section 5. */
+typedef struct {
+    int32_t parts;      /* K, the number of vertex parts (1..255); 0: the smallest K > sub_bins
+                           whose device working set fits the budget (memory cap of the context,
+                           else 90% of the free device memory)                            */
+    int32_t sub_bins;   /* P_GPU: parts resident on the device at a time (2..16; 3)        */
+    int32_t pool_bins;  /* S_GPU: sample pools resident on the device (1..16; 2)          */
+    int32_t B;          /* positives per vertex and part pair in a round (1..31; 5)        */
+    int32_t threads;    /* host sampler threads; 0: all hardware threads (at most 64)      */
+} gosh_part_params;
+
+typedef struct {
+    int32_t parts;          /* K used                                                     */
+    int32_t rounds;         /* ceil(epochs / B)                                           */
+    int64_t positives;      /* positive visits run (at most epochs * n)                   */
+    int64_t pool_entries;   /* pool entries copied to the device (= positives)            */
+    int64_t part_loads;     /* host-to-device part copies                                 */
+    int64_t part_stores;    /* device-to-host part copies                                 */
+    int64_t kernels;        /* pair kernels launched                                      */
+    double h2d_bytes;       /* bytes copied host to device (parts and pools)              */
+    double d2h_bytes;       /* bytes copied device to host                                */
+    double seconds;         /* wall time of the call                                      */
+    double sample_seconds;  /* producer time spent building pools                         */
+    double kernel_seconds;  /* sum of pair-kernel durations (kernels may overlap)         */
+    uint64_t device_bytes;  /* device memory held by the context during the run           */
+} gosh_part_stats;
+
+/* Section 5: embeds a graph whose rows and adjacency stay in host memory.
+ * The ids are split into K contiguous parts (part p = [floor(p n/K),
+ * floor((p+1) n/K))).  Each of ceil(epochs/B) rounds runs a kernel K_{i,j}
+ * for every part pair in inside-out order ((0,0), then (a, b+1) while a > b,
+ * else (a+1, 0)); K_{i,j} visits, for every vertex u of part i with c > 0
+ * neighbours in part j, B positives drawn uniformly among them on the host
+ * (Philox: epoch round*B + b, slot j), and for i != j the same for part j
+ * towards part i; each visit applies UpdateEmbed to its positive and to k
+ * negatives drawn on the device uniformly from the opposite part, with
+ * lr' = lr * max(1 - round/rounds, 1e-4).  Positive visits stop after
+ * epochs * n (the pool sequence is cut in order).  With K = 1 and B = 1 this
+ * is gosh_train's Algorithm 3 (for a graph without isolated vertices).
+ * g_host: HOST arrays (offsets n+1 entries, int32 or int64; indices nnz
+ * int32; symmetric, sorted rows, no self-loops; borrowed).  emb_host: HOST
+ * rows [n, d] of dt, updated in place (pinned memory lets the copies run
+ * asynchronously).  Rows move between host and device part by part, at most
+ * sub_bins at a time; pools are built by host threads and copied while
+ * kernels run.  Deterministic mode (gosh_set_deterministic) runs every
+ * kernel on one wave in pool order.  updates_dev (device, may be NULL)
+ * accumulates executed UpdateEmbed calls; stats (host, may be NULL).
+ * Synchronous.  Errors: E_INVALID_ARG, E_CAP_EXCEEDED (no K fits),
+ * E_UNSUPPORTED (a part above 2^27 rows), E_OOM (pinned host buffers). */
+gosh_status gosh_train_partitioned(gosh_ctx* ctx, const gosh_csr* g_host, void* emb_host, gosh_dtype dt,
+                                   int32_t d, int32_t epochs, float lr, int32_t k, int32_t level,
+                                   uint32_t tag, const gosh_part_params* params, uint64_t* updates_dev,
+                                   gosh_part_stats* stats);
+
+/* K chosen by gosh_train_partitioned for n rows under `budget` device bytes
+ * (params->parts > 0 is returned as is), and the device bytes it needs.
+ * Host only. */
+gosh_status gosh_partition_plan(int64_t n, int32_t d, gosh_dtype dt, uint64_t budget,
+                                const gosh_part_params* params, int32_t* parts_out, uint64_t* bytes_out);
+
+/* The K(K+1)/2 part pairs in inside-out order: pairs_out[2q], pairs_out[2q+1].
+ * Host only. */
+gosh_status gosh_inside_out(int32_t K, int32_t* pairs_out);
+
+/* Test hook (host only): pool S_{i,j} of `round` as gosh_train_partitioned
+ * builds it with Philox key `seed`: *count entries (source id, positive id,
+ * b), side i first.  Output arrays (host, may be NULL to count) need
+ * `capacity` entries. */
+gosh_status gosh_partition_pool(const gosh_csr* g_host, int32_t K, int32_t i, int32_t j, int32_t B,
+                                uint64_t seed, int32_t level, uint32_t tag, int32_t round, int32_t threads,
+                                int64_t* count, int32_t* src_out, int32_t* pos_out, int32_t* b_out,
+                                int64_t capacity);
+
 /* ---------------------------------------------------------------- learned prolongation */
 
 /* Creates the prolongation network for rows of width d (32, 64, 128 or 256)

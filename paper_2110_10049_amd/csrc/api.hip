@@ -100,6 +100,21 @@ gosh_status guarded(gosh_ctx* ctx, F&& f) {
     }
 }
 
+// Host-only entry points report their status without a context.
+template <class F>
+gosh_status host_guarded(F&& f) {
+    try {
+        f();
+        return GOSH_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return GOSH_E_OOM;
+    } catch (...) {
+        return GOSH_E_DEVICE;
+    }
+}
+
 void set_device(Ctx* c) { GOSH_HIP(hipSetDevice(c->device)); }
 
 const gosh::Level& level_of(const gosh_levels* lv, int32_t i) {
@@ -515,6 +530,42 @@ gosh_status gosh_mlp_train(gosh_ctx* ctx, gosh_mlp* mlp, gosh_dtype dt, const go
         }
         set_device(&ctx->c);
         gosh::mlp_train(&ctx->c, m, dt, v, steps, batch, lr, tag, loss_dev);
+    });
+}
+
+// ---------------------------------------------------------------- partitioned embedding
+
+gosh_status gosh_train_partitioned(gosh_ctx* ctx, const gosh_csr* g_host, void* emb_host, gosh_dtype dt,
+                                   int32_t d, int32_t epochs, float lr, int32_t k, int32_t level, uint32_t tag,
+                                   const gosh_part_params* params, uint64_t* updates_dev, gosh_part_stats* stats) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        GOSH_REQUIRE(params, GOSH_E_INVALID_ARG, "null parameters");
+        set_device(&ctx->c);
+        gosh::train_partitioned(&ctx->c, g_host, emb_host, dt, d, epochs, lr, k, level, tag, *params, updates_dev,
+                                stats);
+    });
+}
+
+gosh_status gosh_partition_plan(int64_t n, int32_t d, gosh_dtype dt, uint64_t budget, const gosh_part_params* params,
+                                int32_t* parts_out, uint64_t* bytes_out) {
+    if (!params || !parts_out || n < 0) return GOSH_E_INVALID_ARG;
+    return host_guarded([&] { *parts_out = gosh::partition_parts(n, d, dt, budget, *params, bytes_out); });
+}
+
+gosh_status gosh_inside_out(int32_t K, int32_t* pairs_out) {
+    if (!pairs_out) return GOSH_E_INVALID_ARG;
+    return host_guarded([&] { gosh::inside_out_pairs(K, pairs_out); });
+}
+
+gosh_status gosh_partition_pool(const gosh_csr* g_host, int32_t K, int32_t i, int32_t j, int32_t B, uint64_t seed,
+                                int32_t level, uint32_t tag, int32_t round, int32_t threads, int64_t* count,
+                                int32_t* src_out, int32_t* pos_out, int32_t* b_out, int64_t capacity) {
+    if (!count) return GOSH_E_INVALID_ARG;
+    if ((src_out || pos_out || b_out) && !(src_out && pos_out && b_out)) return GOSH_E_INVALID_ARG;
+    return host_guarded([&] {
+        *count = gosh::partition_pool(g_host, K, i, j, B, seed, level, tag, round, threads, src_out, pos_out, b_out,
+                                      capacity);
     });
 }
 

@@ -13,7 +13,7 @@ namespace gosh {
 // (SC'11): each round multiplies counter words 0 and 2 by fixed odd
 // constants; the high halves are xored with the other two words and the
 // round key, the low halves pass through; the key advances by a Weyl step.
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+__host__ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
     constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
 #pragma unroll
@@ -39,7 +39,7 @@ __host__ __device__ __forceinline__ uint32_t stream_word3(uint32_t kind, uint32_
 }
 
 // floor(r * N / 2^32) for 0 <= N < 2^32
-__device__ __forceinline__ int64_t scale_u32(uint32_t r, int64_t N) {
+__host__ __device__ __forceinline__ int64_t scale_u32(uint32_t r, int64_t N) {
     return static_cast<int64_t>((static_cast<uint64_t>(r) * static_cast<uint64_t>(N)) >> 32);
 }
 

@@ -159,6 +159,16 @@ void prolong_copy(Ctx* c, const Level& fine, const void* coarse, void* fine_emb,
 void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
                    uint64_t* updates_dev, int32_t* chosen);
 void free_level(Ctx* c, Level& L);
+// (partition.hip)
+void train_partitioned(Ctx* c, const gosh_csr* g_host, void* emb_host, gosh_dtype dt, int d, int epochs,
+                       float lr, int k, int32_t level, uint32_t tag, const gosh_part_params& p,
+                       uint64_t* updates_dev, gosh_part_stats* stats);
+int partition_parts(int64_t n, int d, gosh_dtype dt, uint64_t budget, const gosh_part_params& p,
+                    uint64_t* bytes);
+int64_t partition_pool(const gosh_csr* g, int K, int i, int j, int B, uint64_t seed, int32_t level,
+                       uint32_t tag, int32_t round, int threads, int32_t* src, int32_t* pos, int32_t* b,
+                       int64_t capacity);
+void inside_out_pairs(int K, int32_t* out);
 // (mlp.hip)
 gosh_mlp* mlp_create(gosh_ctx* owner, int d, int hidden);
 void mlp_free(gosh_mlp* M);

@@ -40,6 +40,22 @@ class gosh_job(C.Structure):
 GOSH_BATCH_AUTO, GOSH_BATCH_PERSISTENT, GOSH_BATCH_EPOCH_GRAPH = 0, 1, 2
 
 
+class gosh_part_params(C.Structure):
+    _fields_ = [("parts", C.c_int32), ("sub_bins", C.c_int32), ("pool_bins", C.c_int32), ("B", C.c_int32),
+                ("threads", C.c_int32)]
+
+
+class gosh_part_stats(C.Structure):
+    _fields_ = [("parts", C.c_int32), ("rounds", C.c_int32), ("positives", C.c_int64),
+                ("pool_entries", C.c_int64), ("part_loads", C.c_int64), ("part_stores", C.c_int64),
+                ("kernels", C.c_int64), ("h2d_bytes", C.c_double), ("d2h_bytes", C.c_double),
+                ("seconds", C.c_double), ("sample_seconds", C.c_double), ("kernel_seconds", C.c_double),
+                ("device_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class gosh_mlp_batch(C.Structure):
     _fields_ = [("rows", C.c_int64), ("coarse", C.c_void_p), ("deg", C.c_void_p), ("clsz", C.c_void_p),
                 ("target", C.c_void_p)]
@@ -76,6 +92,15 @@ _SIGNATURES = [
     ("gosh_train_batched", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
                                      C.c_int, _P, C.POINTER(C.c_int32)]),
     ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32, _P]),
+    ("gosh_train_partitioned", C.c_int, [_P, C.POINTER(gosh_csr), _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
+                                         C.c_int32, C.c_int32, C.c_uint32, C.POINTER(gosh_part_params), _P,
+                                         C.POINTER(gosh_part_stats)]),
+    ("gosh_partition_plan", C.c_int, [C.c_int64, C.c_int32, C.c_int, C.c_uint64, C.POINTER(gosh_part_params),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
+    ("gosh_inside_out", C.c_int, [C.c_int32, _P]),
+    ("gosh_partition_pool", C.c_int, [C.POINTER(gosh_csr), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                      C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.POINTER(C.c_int64), _P, _P, _P,
+                                      C.c_int64]),
     ("gosh_mlp_create", C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(_P)]),
     ("gosh_mlp_destroy", C.c_int, [_P]),
     ("gosh_mlp_num_params", C.c_int, [_P, C.POINTER(C.c_int64)]),
@@ -417,3 +442,73 @@ def gosh_train_batched(ctx: Context, jobs, k: int, mode: int = GOSH_BATCH_AUTO,
     u = _dev(updates, torch.int64, "updates") if updates is not None else None
     ctx.check(lib().gosh_train_batched(ctx.h, arr, len(jobs), _dtype_code(jobs[0][1]), d, k, mode, u, chosen))
     return tuple(chosen)
+
+
+# ------------------------------------------------------------------ partitioned embedding (Section 5)
+def part_params(parts=0, sub_bins=3, pool_bins=2, B=5, threads=0) -> gosh_part_params:
+    return gosh_part_params(parts, sub_bins, pool_bins, B, threads)
+
+
+class HostCSR:
+    """A gosh_csr view of HOST numpy arrays (kept alive here)."""
+
+    def __init__(self, offsets, indices):
+        import numpy as np
+        self.offsets = np.ascontiguousarray(offsets)
+        if self.offsets.dtype not in (np.int32, np.int64):
+            self.offsets = self.offsets.astype(np.int64)
+        self.indices = np.ascontiguousarray(indices, dtype=np.int32)
+        self.view = gosh_csr(len(self.offsets) - 1, len(self.indices), self.offsets.ctypes.data,
+                             1 if self.offsets.dtype == np.int64 else 0, self.indices.ctypes.data)
+
+
+def _raise_host(st, what):
+    if st != 0:
+        raise GoshError(st, what)
+
+
+def gosh_inside_out(K: int):
+    import numpy as np
+    buf = np.zeros(max(K * (K + 1), 2), np.int32)
+    _raise_host(lib().gosh_inside_out(K, buf.ctypes.data), "bad part count")
+    return [(int(buf[2 * q]), int(buf[2 * q + 1])) for q in range(K * (K + 1) // 2)]
+
+
+def gosh_partition_plan(n: int, d: int, dtype: torch.dtype, budget: int, params: gosh_part_params):
+    K = C.c_int32()
+    b = C.c_uint64()
+    code = GOSH_BF16 if dtype == torch.bfloat16 else GOSH_F32
+    _raise_host(lib().gosh_partition_plan(n, d, code, budget, C.byref(params), C.byref(K), C.byref(b)),
+                "no plan fits")
+    return K.value, b.value
+
+
+def gosh_partition_pool(g: HostCSR, K: int, i: int, j: int, B: int, seed: int, level: int = 0, tag: int = 0,
+                        round: int = 0, threads: int = 0):
+    """Pool S_{i,j} of a round as the library builds it: (src, pos, b) arrays."""
+    import numpy as np
+    cnt = C.c_int64()
+    _raise_host(lib().gosh_partition_pool(C.byref(g.view), K, i, j, B, seed, level, tag, round, threads,
+                                          C.byref(cnt), None, None, None, 0), "bad pool request")
+    m = cnt.value
+    src, pos, bb = (np.zeros(max(m, 1), np.int32) for _ in range(3))
+    _raise_host(lib().gosh_partition_pool(C.byref(g.view), K, i, j, B, seed, level, tag, round, threads,
+                                          C.byref(cnt), src.ctypes.data, pos.ctypes.data, bb.ctypes.data, m),
+                "bad pool request")
+    return src[:m], pos[:m], bb[:m]
+
+
+def gosh_train_partitioned(ctx: Context, g: HostCSR, emb: torch.Tensor, epochs: int, lr: float, k: int,
+                           level: int = 0, tag: int = 0, params: gosh_part_params | None = None,
+                           updates: torch.Tensor | None = None) -> dict:
+    """Section 5 on a host graph and HOST rows (a CPU tensor, pinned for
+    asynchronous copies), updated in place; returns the run's statistics."""
+    if emb.is_cuda or not emb.is_contiguous() or emb.dim() != 2 or emb.shape[0] != g.view.n:
+        raise ValueError("emb must be a contiguous host tensor [n, d]")
+    params = params or part_params()
+    st = gosh_part_stats()
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    ctx.check(lib().gosh_train_partitioned(ctx.h, C.byref(g.view), C.c_void_p(emb.data_ptr()), _dtype_code(emb),
+                                           emb.shape[1], epochs, lr, k, level, tag, C.byref(params), u,
+                                           C.byref(st)))
+    return st.as_dict()
