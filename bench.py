@@ -69,7 +69,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS) + ["batch512", "mlp"])
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22"])
+    ap.add_argument("--part-epochs", type=int, default=30, help="epochs of the partitioned level-0 run")
+    ap.add_argument("--part-threads", type=int, default=0, help="host sampler threads (0: all)")
     ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "graph"])
     ap.add_argument("--batch-levels-upto", type=int, default=0,
                     help="train levels with at most this many vertices through the batched path")
@@ -308,6 +310,84 @@ def mlp_workload(a):
     print(json.dumps(out), flush=True)
 
 
+def partition_workload(a):
+    """Partitioned embedding of the scale-22 R-MAT train graph's level 0
+    (d = 128, BF16, k = 3, B = 5, P_GPU = 3, S_GPU = 2) under a device-memory
+    cap that makes the plan pick K = 4 parts, against the resident trainer on
+    the same graph and epochs.  value = edge-samples/s of the partitioned
+    run (wall time of the call: host sampling, transfers and kernels).
+    roofline: the pair kernel, algorithmic bytes per visit 2*d*b*(2+k) + 8
+    (rows as in the resident kernel plus the 8-byte pool entry)."""
+    import torch
+
+    from paper_2110_10049_amd import gosh as G
+    from synth import init_rows, split_edges
+    from synth.rmat import rmat_csr_torch
+
+    d, k, lr, B, e = 128, 3, 0.045, 5, a.part_epochs
+    seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4}
+    t0 = time.time()
+    off, idx = rmat_csr_torch(22, 16, seeds["graph"], "cuda")
+    sp = split_edges(off.cpu().numpy(), idx.cpu().numpy(), seeds["split"])
+    del off, idx
+    n, nnz = sp.n, len(sp.indices)
+    log(f"scale 22 train graph: |V|={n} nnz={nnz} ({time.time() - t0:.1f}s)")
+    params = G.part_params(parts=0, sub_bins=3, pool_bins=2, B=B, threads=a.part_threads)
+    K4, need = G.gosh_partition_plan(n, d, torch.bfloat16, 1 << 50, G.part_params(parts=4, B=B))
+    probe = G.Context(0, seed=seeds["philox"])
+    cap = need + probe.mem_in_use()
+    probe.close()
+    ctx = G.Context(0, seed=seeds["philox"], mem_cap=cap)
+    hg = G.HostCSR(sp.offsets, sp.indices)
+    f = init_rows(n, d, seeds["init"])
+    rows = torch.from_numpy(f).to(torch.bfloat16).pin_memory()
+    work = rows.clone().pin_memory()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    G.gosh_train_partitioned(ctx, hg, work, 1, lr, k, params=params)          # warm-up
+    work.copy_(rows)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = G.gosh_train_partitioned(ctx, hg, work, e, lr, k, params=params, updates=cnt)
+    wall = time.perf_counter() - t
+    upd = int(cnt.item())
+    log(f"partitioned: {st}")
+
+    # resident reference on the same graph and epochs (no cap)
+    rctx = G.Context(0, seed=seeds["philox"])
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    lv = G.gosh_levels_single(rctx, g)
+    M = rows.cuda()
+    G.gosh_train(rctx, lv, 0, M, 1, lr, k)
+    M.copy_(rows.cuda())
+    rc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    G.gosh_train(rctx, lv, 0, M, e, lr, k, 0, rc)
+    torch.cuda.synchronize()
+    rwall = time.perf_counter() - t
+    rupd = int(rc.item())
+    per_visit = 2 * d * 2 * (2 + k) + 8
+    ach = st["positives"] * per_visit / st["kernel_seconds"] / 1e9 if st["kernel_seconds"] else 0.0
+    out = {
+        "metric": "edge-samples/s (executed UpdateEmbed calls), partitioned embedding under a device-memory cap",
+        "value": round(upd / wall, 1), "unit": "edge-samples/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale 22 (ef 16) link-prediction train graph level 0 (|V|={n}, nnz={nnz}), "
+                               f"d={d}, k={k}, {e} epochs, lr={lr}, B={B}, P_GPU=3, S_GPU=2, cap={cap} bytes",
+                   "seeds": seeds},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_pair (all launches)",
+                     "bytes_per_visit": per_visit},
+        "partitioned": {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in st.items()},
+        "pcie_gbs": round((st["h2d_bytes"] + st["d2h_bytes"]) / wall / 1e9, 2),
+        "kernel_busy_frac": round(st["kernel_seconds"] / wall, 3),
+        "sampler_busy_frac": round(st["sample_seconds"] / wall, 3),
+        "resident": {"value": round(rupd / rwall, 1), "ms": round(rwall * 1e3, 3), "updates": rupd},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -317,6 +397,8 @@ def main():
         return batch_workload(a)
     if a.workload == "mlp":
         return mlp_workload(a)
+    if a.workload == "part22":
+        return partition_workload(a)
     import torch
 
     from paper_2110_10049_amd import gosh as G

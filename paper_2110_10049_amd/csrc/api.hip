@@ -11,8 +11,7 @@
 namespace gosh {
 
 // ---------------------------------------------------------------- allocator
-namespace {
-size_t bucket(size_t bytes) {
+size_t alloc_bucket(size_t bytes) {
     // 256 B granularity below 1 MiB, then 1/8 power-of-two steps
     if (bytes < (1u << 20)) return (bytes + 255) & ~size_t(255);
     size_t p = 1;
@@ -20,10 +19,9 @@ size_t bucket(size_t bytes) {
     const size_t step = p >> 3;
     return (bytes + step - 1) / step * step;
 }
-}  // namespace
 
 void* Ctx::alloc(size_t bytes) {
-    const size_t b = bucket(bytes == 0 ? 1 : bytes);
+    const size_t b = alloc_bucket(bytes == 0 ? 1 : bytes);
     auto it = cache.lower_bound(b);
     if (it != cache.end() && it->first <= b + b / 4) {
         void* p = it->second;

@@ -57,6 +57,9 @@ struct Ctx {
     void trim();               // releases cached blocks
 };
 
+// Size a device block of `bytes` occupies in the context's allocator.
+size_t alloc_bucket(size_t bytes);
+
 // RAII device buffer tied to a context
 template <class T>
 struct DevBuf {

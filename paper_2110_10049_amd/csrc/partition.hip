@@ -56,7 +56,9 @@ struct PairArgs {
     int64_t start_a, start_b, size_a, size_b;
     uint32_t part_a, part_b;
     const uint2* pool;         // entries: (source local id, positive local id | b << 27)
-    int64_t n0, n1;            // side 0: sources in a, side 1: sources in b
+    int64_t n0, n1;            // entries on the device: side 0 (sources in a), side 1 (sources in b)
+    int64_t f0, f1;            // entries of each side before the positive cap cut the pool
+    int B;
     float lr;
     int k;
     uint32_t key0, key1, w2;
@@ -199,9 +201,20 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs P) {
             __threadfence();
         }
     } else {
+        // A vertex owns B consecutive entries of its side; visiting b-major
+        // (slot i -> vertex i mod m, sample i div m) keeps the B visits of one
+        // source apart instead of in the same wave, where their atomic
+        // commits to the one source row would serialize.
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-        const int64_t e = wave * G + grp;
-        if (e < total) pair_visit<BF16, D, KMAX>(P, e, gl);
+        int64_t i = wave * G + grp;
+        const bool s1 = i >= P.f0;
+        if (s1) i -= P.f0;
+        const int64_t full = s1 ? P.f1 : P.f0;
+        const int64_t m = full / P.B;
+        if (i < full) {
+            const int64_t e = (i % m) * P.B + i / m;
+            if (e < (s1 ? P.n1 : P.n0)) pair_visit<BF16, D, KMAX>(P, s1 ? P.n0 + e : e, gl);
+        }
     }
 }
 
@@ -210,11 +223,10 @@ using PairLauncher = void (*)(const PairArgs&, hipStream_t, bool);
 template <bool BF16, int D, int KMAX>
 void launch_pair(const PairArgs& P, hipStream_t st, bool seq) {
     constexpr int G = 64 / (D / kEPL);
-    const int64_t total = P.n0 + P.n1;
     if (seq) {
         hipLaunchKernelGGL((k_pair<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, P);
     } else {
-        const int64_t blocks = std::max<int64_t>(1, ceil_div(total, (kBlock / 64) * G));
+        const int64_t blocks = std::max<int64_t>(1, ceil_div(P.f0 + P.f1, (kBlock / 64) * G));
         hipLaunchKernelGGL((k_pair<BF16, D, KMAX, false>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, P);
     }
 }
@@ -266,6 +278,10 @@ struct PoolSpec {
     int B;
     uint32_t eps0;                            // round * B
     uint32_t key0, key1, w2;
+    // optional: bounds[u * (K + 1) + p] = position of u's first neighbour >= start of part p,
+    // relative to the row start (the parts never change during a run)
+    const int32_t* bounds = nullptr;
+    int K = 0;
 };
 
 // Runs fn(t) on `threads` threads (the caller's thread is one of them).
@@ -325,8 +341,16 @@ std::pair<int64_t, int64_t> build_pool(const HostGraph& G, const PoolSpec& S, in
             const Side* sp;
             int64_t lo, hi, m = 0;
             range(c, sp, lo, hi);
-            for (int64_t u = lo; u < hi; ++u)
-                if (G.lower(u, sp->o1) > G.lower(u, sp->o0)) m += S.B;
+            if (S.bounds) {
+                const uint32_t o = sp->opp;
+                for (int64_t u = lo; u < hi; ++u) {
+                    const int32_t* bu = S.bounds + u * (S.K + 1);
+                    if (bu[o + 1] > bu[o]) m += S.B;
+                }
+            } else {
+                for (int64_t u = lo; u < hi; ++u)
+                    if (G.lower(u, sp->o1) > G.lower(u, sp->o0)) m += S.B;
+            }
             cnt[c + 1] = m;
         }
     });
@@ -341,8 +365,15 @@ std::pair<int64_t, int64_t> build_pool(const HostGraph& G, const PoolSpec& S, in
             range(c, sp, lo, hi);
             int64_t at = cnt[c];
             for (int64_t u = lo; u < hi; ++u) {
-                const int64_t first = G.lower(u, sp->o0);
-                const int64_t cu = G.lower(u, sp->o1) - first;
+                int64_t first, cu;
+                if (S.bounds) {
+                    const int32_t* bu = S.bounds + u * (S.K + 1);
+                    first = G.beg(u) + bu[sp->opp];
+                    cu = bu[sp->opp + 1] - bu[sp->opp];
+                } else {
+                    first = G.lower(u, sp->o0);
+                    cu = G.lower(u, sp->o1) - first;
+                }
                 if (cu == 0) continue;
                 for (int b = 0; b < S.B; ++b) {
                     const uint4 r = philox10(make_uint4(static_cast<uint32_t>(u), S.eps0 + static_cast<uint32_t>(b),
@@ -377,10 +408,11 @@ int64_t part_start(int64_t n, int K, int p) {
 }
 
 // Device bytes of a plan with K parts.
+// (blocks as the context's allocator sizes them, plus 1 MiB of slack).
 uint64_t plan_bytes(int64_t n, int d, int esz, const gosh_part_params& p, int K) {
-    const int64_t rows = ceil_div(n, K);
-    const uint64_t part = static_cast<uint64_t>(rows) * d * esz;
-    const uint64_t pool = static_cast<uint64_t>(2 * rows) * p.B * sizeof(uint2);
+    const int64_t rows = ceil_div(std::max<int64_t>(n, 1), K);
+    const uint64_t part = alloc_bucket(std::max<size_t>(static_cast<size_t>(rows) * d * esz, 16));
+    const uint64_t pool = alloc_bucket(static_cast<size_t>(std::max<int64_t>(2 * rows * p.B, 1)) * sizeof(uint2));
     return static_cast<uint64_t>(p.sub_bins) * part + static_cast<uint64_t>(p.pool_bins) * pool + (1u << 20);
 }
 
@@ -570,6 +602,25 @@ void train_partitioned(Ctx* c, const gosh_csr* g_host, void* emb_host, gosh_dtyp
     const uint32_t key0 = static_cast<uint32_t>(c->seed), key1 = static_cast<uint32_t>(c->seed >> 32);
     const uint32_t w2 = stream_word2(level, tag);
 
+    // part boundaries inside every row, found once (K+1 binary searches per
+    // vertex) when the table is at most 8 GiB
+    std::vector<int32_t> bounds;
+    if (static_cast<double>(n) * (K + 1) * 4.0 <= 8.0 * (1u << 30)) {
+        Timer tb;
+        bounds.resize(static_cast<size_t>(n) * (K + 1));
+        std::atomic<int64_t> nextv{0};
+        constexpr int64_t kStep = 1 << 14;
+        parallel(threads, [&](int) {
+            for (int64_t v0 = nextv.fetch_add(kStep); v0 < n; v0 = nextv.fetch_add(kStep))
+                for (int64_t u = v0; u < std::min(n, v0 + kStep); ++u) {
+                    const int64_t b0 = G.beg(u);
+                    for (int p = 0; p <= K; ++p)
+                        bounds[static_cast<size_t>(u) * (K + 1) + p] = static_cast<int32_t>(G.lower(u, starts[p]) - b0);
+                }
+        });
+        sample_s += tb.s();
+    }
+
     std::thread producer([&] {
         try {
             for (int64_t q = 0; q < npools; ++q) {
@@ -584,7 +635,7 @@ void train_partitioned(Ctx* c, const gosh_csr* g_host, void* emb_host, gosh_dtyp
                 const auto pr = pairs[q % pairs.size()];
                 PoolSpec ps{starts[pr.first], starts[pr.first + 1], starts[pr.second], starts[pr.second + 1],
                             static_cast<uint32_t>(pr.first), static_cast<uint32_t>(pr.second), B,
-                            static_cast<uint32_t>(rho * B), key0, key1, w2};
+                            static_cast<uint32_t>(rho * B), key0, key1, w2, bounds.empty() ? nullptr : bounds.data(), K};
                 Timer t;
                 auto nn = build_pool(G, ps, threads, static_cast<uint2*>(ring[h]->p), pool_cap);
                 {
@@ -711,7 +762,7 @@ void train_partitioned(Ctx* c, const gosh_csr* g_host, void* emb_host, gosh_dtyp
                 PairArgs A{bins[ba].p, bins[bb].p, starts[pa.first], starts[pa.second],
                            starts[pa.first + 1] - starts[pa.first], starts[pa.second + 1] - starts[pa.second],
                            static_cast<uint32_t>(pa.first), static_cast<uint32_t>(pa.second),
-                           static_cast<const uint2*>(static_cast<const void*>(pools[s].p)), n0, n1,
+                           static_cast<const uint2*>(static_cast<const void*>(pools[s].p)), n0, n1, pr.n0, pr.n1, B,
                            static_cast<float>(lr * std::max(static_cast<double>(f), 1e-4)), k, key0, key1, w2,
                            static_cast<uint32_t>(rho * B), reinterpret_cast<unsigned long long*>(updates_dev)};
                 hipEvent_t t0, t1;
