@@ -69,7 +69,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22"])
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22", "rmat26"])
+    ap.add_argument("--big-scale", type=int, default=26, help="R-MAT scale of the rmat26 workload")
+    ap.add_argument("--big-ef", type=float, default=28, help="R-MAT edge factor of the rmat26 workload")
+    ap.add_argument("--big-cap-gib", type=float, default=16, help="device-memory cap of the partitioned leg")
+    ap.add_argument("--big-lr", type=float, default=0.005,
+                    help="learning rate of the rmat26 workload (0.045 diverges on its level-1 hub)")
     ap.add_argument("--part-epochs", type=int, default=30, help="epochs of the partitioned level-0 run")
     ap.add_argument("--part-threads", type=int, default=0, help="host sampler threads (0: all)")
     ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "graph"])
@@ -388,6 +393,116 @@ def partition_workload(a):
     print(json.dumps(out), flush=True)
 
 
+def big_workload(a):
+    """Friendster-shaped graph: R-MAT scale 26, edge factor 28 (1.88G draws),
+    split 80/20 for link prediction on the device (train graph: int64
+    offsets, int32 indices), d = 128, BF16 rows, k = 3, e = 1000, p = 0.3.
+    (a) resident: coarsening, training of every level and copy prolongation
+    in device memory; value = edge-samples/s of that whole pass.
+    (b) memory cap: level 0 trained again from the prolonged level-1 rows
+    with the partitioned embedding (graph and rows in host memory, device
+    memory capped, P_GPU = 3, S_GPU = 2, B = 5, K by the plan), its own
+    epochs e_0 of the schedule.  Both scored by link prediction (LR on 500k
+    sampled train pairs, AUC on 1M sampled test pairs).  lr = 0.005: with
+    0.045 the rows of level 1, where one super vertex touches 58% of the
+    level, grow without bound."""
+    import torch
+
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    from synth import init_rows
+    from synth.linkpred import auc_on_pairs_device, make_eval_pairs_torch, split_rmat_torch
+
+    d, k, lr, e, p = 128, 3, a.big_lr, 1000, 0.3
+    seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4, "eval": 5}
+    t0 = time.time()
+    sp = split_rmat_torch(a.big_scale, a.big_ef, seeds["graph"], seeds["split"], "cuda",
+                          progress=lambda msg: log(f"{msg} ({time.time() - t0:.1f}s)"))
+    log(f"graph: |V_train|={sp.n} nnz={sp.indices.numel()} ({time.time() - t0:.1f}s)")
+    pairs = make_eval_pairs_torch(sp, seeds["eval"])
+    off, idx = sp.offsets, sp.indices
+    n, nnz = sp.n, idx.numel()
+    del sp
+    torch.cuda.empty_cache()
+    log(f"eval pairs ready ({time.time() - t0:.1f}s)")
+    ctx = G.Context(0, seed=seeds["philox"])
+    g = G.CSR(off, idx)
+    cfg = EmbedConfig(d=d, epochs=e, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=100)
+    # warm-up: every kernel once on a small graph
+    from synth.rmat import rmat_csr_torch
+    wo, wi = rmat_csr_torch(14, 16, 9, "cuda")
+    wo, wi = wo.contiguous(), wi.contiguous()
+    embed(ctx, G.CSR(wo, wi), EmbedConfig(d=d, epochs=20, p=p, lr=lr, k=k, dtype=torch.bfloat16),
+          lambda nn, dd: torch.from_numpy(init_rows(nn, dd, 1)).cuda().to(torch.bfloat16))
+    torch.cuda.synchronize()
+    del wo, wi
+
+    def init_fn(nn, dd):
+        return torch.from_numpy(init_rows(nn, dd, seeds["init"])).cuda().to(torch.bfloat16)
+
+    t = time.perf_counter()
+    res = embed(ctx, g, cfg, init_fn, level_events=True, keep_levels=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    upd = int(res.updates.item())
+    tev = res.timings["train_events"]
+    train_ms = {i: s_.elapsed_time(e_) for i, (s_, e_) in tev.items()}
+    log(f"resident: {wall:.2f} s, {upd / wall / 1e9:.3f} G edge-samples/s, levels {res.sizes}, "
+        f"schedule {res.schedule}, level-0 train {train_ms[0]:.1f} ms")
+    auc_a = auc_on_pairs_device(res.emb, pairs)
+    log(f"resident AUC {auc_a:.4f}")
+    e0 = res.schedule[0]
+    per_src = 2 * d * 2 * (2 + k) + 2 * 8 + 4
+    l0_launch = train_ms[0] / 1e3 / max(e0, 1)
+    ach = n * per_src / l0_launch / 1e9
+
+    # (b) level 0 again from the prolonged level-1 rows, partitioned under the cap
+    fine = torch.empty((n, d), dtype=torch.bfloat16, device="cuda")
+    G.gosh_prolong(ctx, res.levels, 0, res.trained[1], fine)
+    host_rows = torch.empty((n, d), dtype=torch.bfloat16).pin_memory()
+    host_rows.copy_(fine)
+    hoff, hidx = off.cpu().numpy(), idx.cpu().numpy()
+    del fine
+    res.emb = None
+    res.trained.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    hg = G.HostCSR(hoff, hidx)
+    cap = int(a.big_cap_gib * (1 << 30))
+    cctx = G.Context(0, seed=seeds["philox"], mem_cap=cap)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    t = time.perf_counter()
+    st = G.gosh_train_partitioned(cctx, hg, host_rows, e0, lr, k, level=0, tag=0,
+                                  params=G.part_params(sub_bins=3, pool_bins=2, B=5), updates=cnt)
+    pwall = time.perf_counter() - t
+    pupd = int(cnt.item())
+    log(f"partitioned level 0: {pwall:.2f} s, {pupd / pwall / 1e9:.3f} G edge-samples/s, {st}")
+    emb_b = host_rows.cuda()
+    auc_b = auc_on_pairs_device(emb_b, pairs)
+    log(f"partitioned AUC {auc_b:.4f}")
+    pach = st["positives"] * (2 * d * 2 * (2 + k) + 8) / st["kernel_seconds"] / 1e9 if st["kernel_seconds"] else 0.0
+    out = {
+        "metric": "edge-samples/s (executed UpdateEmbed calls) of the whole hot path at d=128",
+        "value": round(upd / wall, 1), "unit": "edge-samples/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {a.big_scale} ef {a.big_ef} link-prediction train graph (|V|={n}, "
+                               f"nnz={nnz}, int64 offsets), d={d}, k={k}, e={e}, p={p}, lr={lr}, BF16 rows",
+                   "levels": res.sizes, "schedule": res.schedule, "seeds": seeds,
+                   "eval": "LR on 500k sampled train pairs, AUC on 1M sampled test pairs"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_train level 0",
+                     "launch_us": round(l0_launch * 1e6, 1)},
+        "train_ms_per_level": {str(i): round(v, 2) for i, v in train_ms.items()},
+        "auc": {"resident": round(auc_a, 4), "partitioned_level0": round(auc_b, 4)},
+        "capped": {"cap_bytes": cap, "seconds": round(pwall, 3), "value": round(pupd / pwall, 1),
+                   "epochs": e0, "pcie_gbs": round((st["h2d_bytes"] + st["d2h_bytes"]) / pwall / 1e9, 2),
+                   "pair_kernel_gbs": round(pach, 1),
+                   "stats": {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in st.items()}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -399,6 +514,8 @@ def main():
         return mlp_workload(a)
     if a.workload == "part22":
         return partition_workload(a)
+    if a.workload == "rmat26":
+        return big_workload(a)
     import torch
 
     from paper_2110_10049_amd import gosh as G

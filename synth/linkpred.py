@@ -137,3 +137,187 @@ def evaluate_auc(emb: np.ndarray, split: LinkSplit, seed: int,
                  max_train: int = 2_000_000, max_test: int | None = None) -> float:
     """AUCROC of a logistic-regression link predictor on Hadamard features."""
     return auc_on_pairs(emb, make_eval_pairs(split, seed, max_train, max_test))
+
+
+# --------------------------------------------------------------------------- device (torch) versions
+# For graphs too large for the host-side split above (billions of edges) the
+# same protocol runs on torch tensors, with one change: an edge goes to the
+# test set when a seeded hash of its key falls below 0.2 (an independent
+# Bernoulli(0.2) draw per edge) instead of by a shuffled 80/20 cut.
+
+def _s64(x: int) -> int:
+    """uint64 value as the int64 with the same bits."""
+    x &= (1 << 64) - 1
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+_GOLD, _M1, _M2 = _s64(0x9E3779B97F4A7C15), _s64(0xBF58476D1CE4E5B9), _s64(0x94D049BB133111EB)   # SplitMix64
+
+
+def _lsr(z, k: int):
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _mix64(z):
+    """SplitMix64 output function on int64 tensors holding uint64 bits."""
+    z = z + _GOLD
+    z = (z ^ _lsr(z, 30)) * _M1
+    z = (z ^ _lsr(z, 27)) * _M2
+    return z ^ _lsr(z, 31)
+
+
+@dataclass
+class DeviceSplit:
+    n: int                  # |V_train|
+    offsets: object         # int64 [n+1] (device)
+    indices: object         # int32 [nnz] (device)
+    train_keys: object      # int64 sorted u*n+v (u < v, relabelled): the train edges
+    test_keys: object       # int64 sorted u*n+v (u < v, relabelled): test edges inside V_train
+    old_id: object          # int64 old id of each train vertex
+
+
+def split_rmat_torch(scale: int, edge_factor: float, seed: int, split_seed: int, device,
+                     test_frac: float = 0.2, chunk: int = 1 << 26, progress=None) -> DeviceSplit:
+    """R-MAT graph (as rmat_csr) split for link prediction on `device`;
+    progress(msg) is called after each stage when given."""
+    say = progress or (lambda msg: None)
+    import torch
+    from .rmat import rmat_pairs_torch
+    N = 1 << scale
+    m = int(round(edge_factor * N))
+    parts = []
+    first = 0
+    while first < m:
+        cnt = min(chunk, m - first)
+        r, c = rmat_pairs_torch(scale, first, cnt, seed, device)
+        first += cnt
+        keep = r != c
+        lo, hi = torch.minimum(r[keep], c[keep]), torch.maximum(r[keep], c[keep])
+        del r, c, keep
+        parts.append(torch.unique(lo * N + hi))
+        del lo, hi
+        if len(parts) % 8 == 0:
+            say(f"drew {first} of {m} pairs")
+    keys = torch.unique(torch.cat(parts))
+    del parts
+    say(f"{keys.numel()} distinct undirected edges")
+    # test iff the hash, read as an unsigned number, is below test_frac * 2^64;
+    # xor with the sign bit makes signed order equal unsigned order
+    salt = _s64(split_seed * 0x9E3779B97F4A7C15)
+    h = _mix64(keys ^ salt)
+    thr = _s64(int(test_frac * 2.0 ** 64) ^ (1 << 63))
+    is_test = (h ^ _s64(1 << 63)) < thr
+    del h
+    test = keys[is_test]
+    train = keys[~is_test]
+    del keys, is_test
+    tu, tv = torch.div(train, N, rounding_mode="floor"), None
+    tv = train - tu * N
+    used = torch.zeros(N, dtype=torch.bool, device=device)
+    used[tu] = True
+    used[tv] = True
+    newid = torch.cumsum(used.to(torch.int64), 0) - 1
+    n = int(used.sum().item())
+    old_id = torch.nonzero(used).flatten()
+    tu, tv = newid[tu], newid[tv]
+    train_keys = tu * n + tv                      # relabelling is monotone: still sorted, u < v
+    del train
+    # CSR without sorting both directions at once: row x holds its smaller
+    # neighbours (the reversed keys v*n+u, sorted) followed by its larger
+    # ones (train_keys, already sorted); both blocks ascend and every smaller
+    # neighbour precedes every larger one
+    say(f"building the CSR of {2 * train_keys.numel()} train entries")
+    rev, _ = torch.sort(tv * n + tu)
+    del tu, tv
+    rows_hi = torch.div(train_keys, n, rounding_mode="floor")
+    rows_lo = torch.div(rev, n, rounding_mode="floor")
+    deg_hi = torch.bincount(rows_hi, minlength=n)
+    deg_lo = torch.bincount(rows_lo, minlength=n)
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offsets[1:] = torch.cumsum(deg_lo + deg_hi, 0)
+    start_lo = torch.cumsum(deg_lo, 0) - deg_lo
+    start_hi = torch.cumsum(deg_hi, 0) - deg_hi
+    indices = torch.empty(int(offsets[-1].item()), dtype=torch.int32, device=device)
+    i = torch.arange(rev.numel(), device=device, dtype=torch.int64)
+    indices[offsets[rows_lo] + (i - start_lo[rows_lo])] = (rev - rows_lo * n).to(torch.int32)
+    del i, rev, rows_lo
+    j = torch.arange(train_keys.numel(), device=device, dtype=torch.int64)
+    indices[offsets[rows_hi] + deg_lo[rows_hi] + (j - start_hi[rows_hi])] = (train_keys - rows_hi * n).to(torch.int32)
+    del j, rows_hi, deg_lo, deg_hi, start_lo, start_hi
+    su = torch.div(test, N, rounding_mode="floor")
+    sv = test - su * N
+    ok = used[su] & used[sv]
+    test_keys = newid[su[ok]] * n + newid[sv[ok]]
+    del su, sv, ok, test, used, newid
+    return DeviceSplit(n, offsets, indices, train_keys, test_keys, old_id)
+
+
+def _contains(sorted_keys, q):
+    import torch
+    if sorted_keys.numel() == 0:
+        return torch.zeros_like(q, dtype=torch.bool)
+    pos = torch.searchsorted(sorted_keys, q).clamp_(max=sorted_keys.numel() - 1)
+    return sorted_keys[pos] == q
+
+
+def _negatives(n, count, forbidden, gen, device):
+    import torch
+    out = []
+    have = 0
+    while have < count:
+        need = count - have
+        u = torch.randint(0, n, (2 * need + 16,), generator=gen, device=device)
+        v = torch.randint(0, n, (2 * need + 16,), generator=gen, device=device)
+        ok = u != v
+        u, v = u[ok], v[ok]
+        key = torch.minimum(u, v) * n + torch.maximum(u, v)
+        bad = torch.zeros_like(key, dtype=torch.bool)
+        for f in forbidden:
+            bad |= _contains(f, key)
+        pairs = torch.stack([u[~bad], v[~bad]], 1)[:need]
+        out.append(pairs)
+        have += len(pairs)
+    return torch.cat(out)
+
+
+def make_eval_pairs_torch(split: DeviceSplit, seed: int, n_train: int = 500_000, n_test: int = 1_000_000):
+    """Classifier and test pairs of the link-prediction protocol on the
+    device split: n_train/2 train edges and as many non-edges of G_train;
+    n_test/2 test edges and as many pairs outside train and test edges."""
+    import torch
+    dev = split.train_keys.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    n = split.n
+
+    def pick(keys, count):
+        sel = torch.randint(0, keys.numel(), (count,), generator=gen, device=dev)
+        k = keys[sel]
+        u = torch.div(k, n, rounding_mode="floor")
+        return torch.stack([u, k - u * n], 1)
+
+    ptr = pick(split.train_keys, n_train // 2)
+    ntr = _negatives(n, n_train // 2, [split.train_keys], gen, dev)
+    pte = pick(split.test_keys, n_test // 2)
+    nte = _negatives(n, n_test // 2, [split.train_keys, split.test_keys], gen, dev)
+    xtr = torch.cat([ptr, ntr]).cpu().numpy()
+    ytr = np.concatenate([np.ones(len(ptr)), np.zeros(len(ntr))])
+    xte = torch.cat([pte, nte]).cpu().numpy()
+    yte = np.concatenate([np.ones(len(pte)), np.zeros(len(nte))])
+    return EvalPairs(xtr, ytr, xte, yte)
+
+
+def auc_on_pairs_device(emb, P: EvalPairs) -> float:
+    """auc_on_pairs with the Hadamard features gathered on the embedding's
+    device (only the pairs' rows leave it)."""
+    import torch
+    from sklearn.linear_model import LogisticRegression
+    from sklearn.metrics import roc_auc_score
+
+    def feats(x):
+        idx = torch.from_numpy(x).to(emb.device)
+        return (emb[idx[:, 0]].float() * emb[idx[:, 1]].float()).cpu().numpy().astype(np.float64)
+
+    clf = LogisticRegression(max_iter=1000)
+    clf.fit(feats(P.xtr), P.ytr)
+    return float(roc_auc_score(P.yte, clf.decision_function(feats(P.xte))))

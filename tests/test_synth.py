@@ -118,3 +118,36 @@ def test_drop_isolated_torch():
     a = np.sort(old[src] * n0 + old[x])
     s0 = np.repeat(np.arange(n0), np.diff(off))
     assert np.array_equal(a, np.sort(s0 * n0 + idx))
+
+
+def test_device_split_protocol():
+    # the torch split on the CPU device: train and test partition the edges,
+    # the train CSR is valid, relabelling keeps old-id order, negatives avoid edges
+    import torch
+    from synth.linkpred import make_eval_pairs_torch, split_rmat_torch
+    sp = split_rmat_torch(11, 8, 1, 2, "cpu", chunk=5000)
+    off, idx = sp.offsets.numpy(), sp.indices.numpy()
+    check_csr(off, idx)
+    assert np.all(np.diff(off) > 0) and len(off) == sp.n + 1
+    assert np.all(np.diff(sp.old_id.numpy()) > 0)
+    full_off, full_idx = rmat_csr(11, 8, seed=1)
+    N = len(full_off) - 1
+    src = np.repeat(np.arange(N), np.diff(full_off))
+    allk = np.sort((src * N + full_idx)[src < full_idx])
+    old = sp.old_id.numpy()
+    tr = sp.train_keys.numpy()
+    tu, tv = tr // sp.n, tr % sp.n
+    back = np.sort(old[tu] * N + old[tv])
+    assert np.all(np.isin(back, allk))
+    frac = len(tr) / len(allk)
+    assert 0.78 < frac < 0.82
+    te = sp.test_keys.numpy()
+    assert not np.intersect1d(te, tr).size
+    P = make_eval_pairs_torch(sp, 5, n_train=2000, n_test=2000)
+    trs, tes = set(tr.tolist()), set(te.tolist())
+    for (u, v), y in zip(P.xtr, P.ytr):
+        k = min(u, v) * sp.n + max(u, v)
+        assert (k in trs) == (y == 1) and u != v
+    for (u, v), y in zip(P.xte, P.yte):
+        k = min(u, v) * sp.n + max(u, v)
+        assert (k in tes) == (y == 1) and (k not in trs)
