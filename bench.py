@@ -39,19 +39,22 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_bf16_traffic.m
 
 def measured_traffic():
     """HBM bytes per level-0 launch from the committed counter summary, or
-    None if the training kernel source changed since it was measured."""
+    None if a source of the training kernel changed since it was measured."""
     import hashlib
     try:
         txt = open(TRAFFIC_FILE).read()
+        keys = ("kernel_sources", "kernel_sources_sha256", "traffic_bytes_per_launch")
         fields = dict(l.strip().split(": ", 1) for l in txt.splitlines() if l.startswith("    ") and ": " in l
-                      and l.strip().split(": ", 1)[0] in ("kernel_source", "kernel_source_sha256",
-                                                          "traffic_bytes_per_launch"))
-        src = os.path.join(ROOT, fields["kernel_source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["kernel_source_sha256"]:
+                      and l.strip().split(": ", 1)[0] in keys)
+        h = hashlib.sha256()
+        for rel in fields["kernel_sources"].split(","):
+            h.update(open(os.path.join(ROOT, rel.strip()), "rb").read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
 
 WORKLOADS = {
     # name: (scale, edge factor, d, k, epochs, threshold)
@@ -86,6 +89,7 @@ def parse():
     ap.add_argument("--cpu-sample-epochs", type=int, default=4)
     ap.add_argument("--mlp-steps", type=int, default=2000, help="Adam steps of the prolongation network")
     ap.add_argument("--mlp-budgets", default="75,150,300,600", help="epoch budgets of the learned-vs-copy sweep")
+    ap.add_argument("--mlp-no-eval", action="store_true", help="skip the link-prediction sweep (kernel timing only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -273,6 +277,10 @@ def mlp_workload(a):
                    "flops_per_row": flops_fwd, "bytes_per_row": bytes_row}
     log(f"mlp prolong: {mlp_prolong}")
 
+    if a.mlp_no_eval:
+        print(json.dumps({"metric": "learned prolongation kernel", "mlp_train": mlp_train,
+                          "mlp_prolong": mlp_prolong}), flush=True)
+        return
     t = time.time()
     pairs = make_eval_pairs(sp22, seeds["eval"], max_train=500_000, max_test=1_000_000)
     log(f"eval pairs ready ({time.time() - t:.1f}s)")
