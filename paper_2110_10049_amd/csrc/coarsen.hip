@@ -140,6 +140,37 @@ __global__ void k_round(int64_t n, const int64_t* lstart, const int32_t* lower, 
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(undecided, cnt);
 }
 
+// The same decision with one wave per vertex, for dense levels whose
+// segments run to hundreds of entries: lanes split the segment, ballots
+// combine (reading every entry instead of stopping at the first IN gives the
+// same decision).
+__global__ void k_round_wave(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
+                             unsigned long long* undecided) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    unsigned long long cnt = 0;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); v < n;
+         v += static_cast<int64_t>(gridDim.x) * wpb) {
+        const uint8_t sv = state[v];
+        if (sv != kUndecided) continue;   // one address: the same value in every lane
+        bool any_in = false, pending = false;
+        const int64_t e = lstart[v + 1];
+        for (int64_t i = lstart[v] + lane; i < e; i += 64) {
+            const uint8_t su = state[lower[i]];
+            any_in |= (su == kIn);
+            pending |= (su == kUndecided);
+        }
+        const bool w_in = __ballot(any_in) != 0ull;
+        const bool w_pending = __ballot(pending) != 0ull;
+        if (lane == 0) {
+            if (w_in) state[v] = kOut;
+            else if (!w_pending) state[v] = kIn;
+            else ++cnt;
+        }
+    }
+    if (lane == 0 && cnt) atomicAdd(undecided, cnt);
+}
+
 __global__ void k_hub_flags_by_rank(const uint32_t* perm, int64_t n, const uint8_t* state, int32_t* hf) {
     GRID_STRIDE(r, n) hf[r] = state[perm[r]] == kIn ? 1 : 0;
 }
@@ -166,6 +197,37 @@ __global__ void k_assign(int64_t n, const int64_t* lstart, const int32_t* lower,
             continue;
         }
         map[v] = static_cast<int32_t>(cid_by_rank[r]);
+    }
+}
+
+// k_assign with one wave per vertex (dense levels): lanes take the minimum
+// hub rank over their part of the segment, then the wave reduces it.
+__global__ void k_assign_wave(int64_t n, const int64_t* lstart, const int32_t* lower, const uint8_t* state,
+                              const int32_t* rank, const int64_t* cid_by_rank, int32_t* map, unsigned int* bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); v < n;
+         v += static_cast<int64_t>(gridDim.x) * wpb) {
+        const uint8_t sv = state[v];
+        int32_t best = INT32_MAX;
+        if (sv == kIn) {
+            best = rank[v];
+        } else if (sv == kOut) {
+            const int64_t e = lstart[v + 1];
+            for (int64_t i = lstart[v] + lane; i < e; i += 64) {
+                const int32_t u = lower[i];
+                if (state[u] == kIn) best = min(best, rank[u]);
+            }
+            for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+        }
+        if (lane == 0) {
+            if (best < 0 || best >= n) {   // cannot happen once every vertex is decided
+                map[v] = 0;
+                atomicOr(bad, 1u);
+            } else {
+                map[v] = static_cast<int32_t>(cid_by_rank[best]);
+            }
+        }
     }
 }
 
@@ -450,13 +512,19 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
 
     // hub selection rounds; each round decides at least the earliest
     // undecided vertex, so the loop ends
+    // dense levels (average degree >= 64) scan each segment with a whole wave
+    const bool dense = nnz >= 64 * n;
     DevBuf<uint8_t> state(c, n);
     fill(c, state.p, n, 0);
     for (int64_t round = 0;; ++round) {
         GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
         GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
-        hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                           scratch_u64(c, 1));
+        if (dense)
+            hipLaunchKernelGGL(k_round_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
+                               lower.p, state.p, scratch_u64(c, 1));
+        else
+            hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                               scratch_u64(c, 1));
         GOSH_HIP(hipGetLastError());
         if (read_u64(c, scratch_u64(c, 1)) == 0) break;
     }
@@ -473,8 +541,12 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
     unsigned int* bad = reinterpret_cast<unsigned int*>(scratch_u64(c, 4));
     GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                       rank.p, cid.p, L.map, bad);
+    if (dense)
+        hipLaunchKernelGGL(k_assign_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
+                           lower.p, state.p, rank.p, cid.p, L.map, bad);
+    else
+        hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                           rank.p, cid.p, L.map, bad);
     GOSH_HIP(hipGetLastError());
     cid.reset();
     state.reset();

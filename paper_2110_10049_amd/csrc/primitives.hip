@@ -64,6 +64,42 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_reduce(const T* in, int64
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
+// A thread's kScanItems consecutive items: 16-byte accesses when the run is
+// whole and aligned (the scans are bandwidth-bound), element-wise otherwise.
+template <class T>
+__device__ __forceinline__ void load_run(const T* in, int64_t start, int64_t n, int64_t (&v)[kScanItems]) {
+    static_assert(kScanItems * sizeof(T) % 16 == 0, "whole 16-byte chunks");
+    if (start + kScanItems <= n && (reinterpret_cast<uintptr_t>(in + start) & 15u) == 0) {
+        constexpr int per = 16 / sizeof(T);
+#pragma unroll
+        for (int c = 0; c < kScanItems / per; ++c) {
+            const int4 w = reinterpret_cast<const int4*>(in + start)[c];
+            T t[per];
+            __builtin_memcpy(t, &w, 16);
+#pragma unroll
+            for (int j = 0; j < per; ++j) v[c * per + j] = static_cast<int64_t>(t[j]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[i] = start + i < n ? static_cast<int64_t>(in[start + i]) : 0;
+    }
+}
+
+__device__ __forceinline__ void store_run(int64_t* out, int64_t start, int64_t n, const int64_t (&r)[kScanItems]) {
+    if (start + kScanItems <= n && (reinterpret_cast<uintptr_t>(out + start) & 15u) == 0) {
+#pragma unroll
+        for (int c = 0; c < kScanItems / 2; ++c) {
+            int4 w;
+            __builtin_memcpy(&w, &r[2 * c], 16);
+            reinterpret_cast<int4*>(out + start)[c] = w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+            if (start + i < n) out[start + i] = r[i];
+    }
+}
+
 // Scans one tile per block (blocked arrangement: thread t owns items
 // [t*kScanItems, (t+1)*kScanItems) of the tile), adding prefix[block].
 template <class T, ScanOp OP>
@@ -72,23 +108,21 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const T* in, int64_t
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     const int64_t start = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
+    load_run(in, start, n, v);
     int64_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = start + i;
-        v[i] = idx < n ? static_cast<int64_t>(in[idx]) : 0;
-        acc = apply<OP>(acc, v[i]);
-    }
+    for (int i = 0; i < kScanItems; ++i) acc = apply<OP>(acc, v[i]);
     int64_t total;
     int64_t run = block_exclusive<OP>(acc, &total);
     if (prefix) run = apply<OP>(prefix[blockIdx.x], run);
+    int64_t r[kScanItems];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = start + i;
         const int64_t nxt = apply<OP>(run, v[i]);
-        if (idx < n) out[idx] = inclusive ? nxt : run;
+        r[i] = inclusive ? nxt : run;
         run = nxt;
     }
+    store_run(out, start, n, r);
 }
 
 template <class T, ScanOp OP>

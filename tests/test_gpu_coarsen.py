@@ -90,6 +90,17 @@ def test_long_chain_path(gctx, orc):
     _compare(gctx, orc, off, idx, threshold=4)
 
 
+@pytest.mark.parametrize("n,prob,seed", [(200, 1.0, 0), (500, 0.3, 1), (3000, 0.05, 2)])
+def test_dense_graphs(gctx, orc, n, prob, seed):
+    # average degree >= 64: hub rounds and the assignment run one wave per vertex
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(len(iu)) < prob
+    off, idx = csr_from_pairs(n, iu[keep], ju[keep])
+    assert len(idx) >= 64 * n
+    _compare(gctx, orc, off, idx, threshold=2)
+
+
 def test_edgeless_and_isolated(gctx, orc):
     off = np.zeros(9, np.int64)
     _compare(gctx, orc, off, np.zeros(0, np.int32), threshold=2)
