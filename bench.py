@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--batch-mode", default="auto", choices=["auto", "persistent", "graph"])
     ap.add_argument("--batch-levels-upto", type=int, default=0,
                     help="train levels with at most this many vertices through the batched path")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="epochs per launch on levels of at least --overlap-min vertices (1: one epoch per launch)")
+    ap.add_argument("--overlap-min", type=int, default=65536)
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -546,6 +549,7 @@ def main():
         torch.cuda.synchronize()
         del src_buf, dst_buf
     ctx = G.Context(0, seed=seeds["philox"])
+    ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
 
@@ -618,6 +622,7 @@ def main():
                                f"(|V|={n0}, nnz={len(sp.indices)}), d={d}, k={k}, e={epochs}, p={p}, "
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
+                   "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" else None),
         "train_ms_per_step": round(bf["train_ms"], 3),

@@ -90,6 +90,16 @@ gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes);
  * sources of an epoch run concurrently without locks (Section 3.1). */
 gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on);
 
+/* Concurrent epochs on large levels (the extension the paper suggests in
+ * Section 6.3: overlapping epochs on the upper levels, full synchronisation
+ * elsewhere): gosh_train runs `epochs_in_flight` consecutive epochs in one
+ * launch, with no barrier between them, on levels of at least
+ * `min_vertices` vertices; smaller levels keep one epoch per launch.  Each
+ * visit keeps its own epoch's samples and lr.  1 (the default) restores
+ * Algorithm 3's barriers everywhere.  Ignored in deterministic mode.
+ * epochs_in_flight in [1, 64], min_vertices >= 0. */
+gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int64_t min_vertices);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* Checks `g` against the graph convention (Section 4.1: the method works on

@@ -219,6 +219,13 @@ gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on) {
     return GOSH_OK;
 }
 
+gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int64_t min_vertices) {
+    if (!ctx || epochs_in_flight < 1 || epochs_in_flight > 64 || min_vertices < 0) return GOSH_E_INVALID_ARG;
+    ctx->c.overlap = epochs_in_flight;
+    ctx->c.overlap_min = min_vertices;
+    return GOSH_OK;
+}
+
 gosh_status gosh_validate_csr(gosh_ctx* ctx, const gosh_csr* g, int check_symmetry) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     return guarded(ctx, [&] {

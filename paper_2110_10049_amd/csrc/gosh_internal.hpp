@@ -42,6 +42,8 @@ struct Ctx {
     uint64_t cap = 0;          // 0 = unlimited
     uint64_t in_use = 0;       // bytes held by live allocations and the cache
     bool deterministic = false;
+    int overlap = 1;           // epochs per launch on large levels (1: Algorithm 3's barriers)
+    int64_t overlap_min = 0;   // levels with at least this many vertices overlap
     std::string err;
     // Size-bucketed cache of freed device blocks, reused before hipMalloc.
     std::multimap<size_t, void*> cache;

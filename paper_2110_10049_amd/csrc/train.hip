@@ -52,6 +52,18 @@ __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
     } else {
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
         const int64_t slot = wave * G + grp;
+        if constexpr (MODE == kEpoch) {
+            if (P.span > 1) {
+                // several epochs in flight: this slot's epoch and its decayed lr
+                const int64_t ep = slot / P.n;
+                TrainParams Q = P;
+                Q.epoch = P.epoch + static_cast<uint32_t>(ep);
+                const double f = 1.0 - static_cast<double>(Q.epoch) / static_cast<double>(P.e_total);
+                Q.lr = static_cast<float>(static_cast<double>(P.lr0) * (f > 1e-4 ? f : 1e-4));
+                visit<BF16, D, KMAX, Off, MODE>(Q, slot - ep * P.n, slot < P.n * P.span, gl);
+                return;
+            }
+        }
         const int64_t limit = (MODE == kExplicit) ? P.nsrc : P.n;
         visit<BF16, D, KMAX, Off, MODE>(P, slot, slot < limit, gl);
     }
@@ -180,11 +192,18 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     P.updates = reinterpret_cast<unsigned long long*>(updates_dev);
     Launcher fn = c->deterministic ? pick<kSequential>(dt, d, k, L.off64) : pick<kEpoch>(dt, d, k, L.off64);
     GOSH_REQUIRE(fn, GOSH_E_INVALID_ARG, "unsupported training shape");
-    for (int j = 0; j < epochs; ++j) {
+    // epochs run one launch each (Section 3.1), unless the context lets
+    // `overlap` epochs share a launch on levels of at least overlap_min vertices
+    const int span = (!c->deterministic && c->overlap > 1 && L.n >= c->overlap_min) ? c->overlap : 1;
+    P.span = 1;
+    P.e_total = epochs;
+    P.lr0 = lr;
+    for (int j = 0; j < epochs; j += span) {
         const double f = 1.0 - static_cast<double>(j) / static_cast<double>(epochs);
         P.lr = static_cast<float>(static_cast<double>(lr) * (f > 1e-4 ? f : 1e-4));
         P.epoch = static_cast<uint32_t>(j);
-        fn(P, L.n, c->stream);
+        P.span = std::min(span, epochs - j);
+        fn(P, L.n * P.span, c->stream);
         GOSH_HIP(hipGetLastError());
     }
     if (updates_dev) {

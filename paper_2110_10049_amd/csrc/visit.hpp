@@ -32,6 +32,11 @@ struct TrainParams {
     const int32_t* src_list;       // explicit-sample mode
     const int32_t* samples;
     int64_t nsrc;
+    // epochs in one launch (kEpoch mode): slot s runs epoch epoch + s / n with
+    // lr0 * max(1 - epoch / e_total, 1e-4); span 1 uses epoch and lr as given
+    int32_t span;
+    int32_t e_total;
+    float lr0;
 };
 
 enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };

@@ -90,3 +90,43 @@ def test_config1_batched_small_levels_auc(gctx, orc):
     a_o = evaluate_auc(Mo, sp, seed=5)
     print(f"[e2e batched levels] AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
     assert abs(a_g - a_o) < 0.01
+
+
+def test_overlapping_epochs_keep_auc(gctx, orc):
+    # two epochs per launch on the larger levels (Section 6.3's suggestion):
+    # the same number of updates, AUC within 0.01 of the oracle (sequential epochs)
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    sp = train_split(12, 16)
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    cfg = EmbedConfig(d=32, epochs=200, p=0.3, lr=0.045, k=1, threshold=64)
+    gctx.set_epoch_overlap(2, 1000)
+    try:
+        res = embed(gctx, g, cfg, lambda n, dd: torch.from_numpy(init_rows(n, dd, 3)).cuda())
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_epoch_overlap(1, 0)
+    Mo, info = _oracle_embed(orc, sp, 32, 200, 0.3, 0.045, 1, 64, False)
+    assert int(res.updates.item()) == sum(info["updates"])
+    a_g = evaluate_auc(res.emb.cpu().numpy(), sp, seed=5)
+    a_o = evaluate_auc(Mo, sp, seed=5)
+    print(f"[e2e overlapping epochs] AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
+    assert abs(a_g - a_o) < 0.01
+
+
+def test_overlap_with_zero_lr_is_identity(gctx):
+    from paper_2110_10049_amd import gosh as G
+    sp = train_split(12, 16)
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    lv = G.gosh_levels_single(gctx, g)
+    M0 = torch.from_numpy(init_rows(sp.n, 64, 3)).cuda().to(torch.bfloat16)
+    M = M0.clone()
+    gctx.set_epoch_overlap(3, 0)
+    try:
+        G.gosh_train(gctx, lv, 0, M, 7, 0.0, 3)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_epoch_overlap(1, 0)
+    assert torch.equal(M, M0)
+    with pytest.raises(G.GoshError):
+        gctx.set_epoch_overlap(0, 0)
