@@ -555,7 +555,9 @@ def main():
 
     def run(dtype, steps, warmup):
         cfg = EmbedConfig(d=d, epochs=epochs, p=p, lr=lr, k=k, dtype=dtype, threshold=threshold,
-                          batch_levels_upto=a.batch_levels_upto)
+                          batch_levels_upto=a.batch_levels_upto,
+                          batch_mode={"auto": G.GOSH_BATCH_AUTO, "persistent": G.GOSH_BATCH_PERSISTENT,
+                                      "graph": G.GOSH_BATCH_EPOCH_GRAPH}[a.batch_mode])
         lv = G.gosh_coarsen(ctx, g, threshold)
         n_c = lv.sizes()[-1]
         f = init_rows(n_c, d, seeds["init"])

@@ -656,8 +656,6 @@ __global__ void k_sample(const PairSrc* __restrict__ srcs, int nsrc, int64_t tot
 }
 
 // ------------------------------------------------------------ host side
-constexpr int kMaxD = 256, kMaxH = 256;
-
 bool supported(int d, int h) {
     return (d == 32 || d == 64 || d == 128 || d == 256) && (h == 64 || h == 128 || h == 256);
 }

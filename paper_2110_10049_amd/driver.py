@@ -27,6 +27,7 @@ class EmbedConfig:
     # levels with at most this many vertices train through the batched
     # (single persistent launch) path instead of one launch per epoch; 0 = off
     batch_levels_upto: int = 0
+    batch_mode: int = G.GOSH_BATCH_AUTO
 
 
 @dataclass
@@ -69,7 +70,7 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
             ev[0].record(ctx.stream)
         if cfg.batch_levels_upto and sizes[i] <= cfg.batch_levels_upto:
             G.gosh_train_batched(ctx, [(levels.csr(i), M, sched[i], cfg.lr, i, cfg.tag)], cfg.k,
-                                 G.GOSH_BATCH_AUTO, updates=counter)
+                                 cfg.batch_mode, updates=counter)
         else:
             G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
         if level_events:
