@@ -82,6 +82,19 @@ def lib():
                                             C.c_int32, C.c_double, C.c_int32, C.c_uint64, C.c_int32,
                                             C.c_uint32, C.POINTER(C.c_int64)]
         L.orc_train_partitioned.restype = C.c_int64
+        L.orc_walk.argtypes = [_i64p, _i32p, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int64, C.c_int32,
+                               _i32p]
+        L.orc_walk.restype = C.c_int32
+        L.orc_walk_offsets.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        L.orc_walk_offsets.restype = C.c_int32
+        L.orc_walk_order.argtypes = [C.c_int64, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, _i64p]
+        L.orc_walk_order.restype = C.c_int64
+        L.orc_walk_pairs.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32,
+                                     C.c_int32, C.c_int32, _i32p, _i32p]
+        L.orc_walk_pairs.restype = C.c_int64
+        L.orc_train_walks.argtypes = [_i64p, _i32p, C.c_int64, C.POINTER(_Emb), C.c_int32, C.c_double, C.c_int32,
+                                      C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32]
+        L.orc_train_walks.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -316,3 +329,50 @@ def train_partitioned(offsets, indices, M, K, B, epochs, lr, k, seed, level=0, t
     upd = lib().orc_train_partitioned(offsets, indices, n, C.byref(e), K, B, epochs, lr, k, seed, level, tag,
                                       C.byref(pos))
     return int(upd), int(pos.value)
+
+
+# --------------------------------------------------------------------------- random-walk sampling
+def walk(offsets, indices, v, length, seed, level=0, tag=0, epoch=0) -> np.ndarray:
+    offsets, indices = _csr(offsets, indices)
+    out = np.zeros(length + 1, np.int32)
+    m = lib().orc_walk(offsets, indices, seed, level, tag, epoch, v, length, out)
+    return out[:m]
+
+
+def walk_offsets(length, window):
+    """The pair offsets (a, b) of a walk, in pair-number order."""
+    L = lib()
+    P = L.orc_walk_offsets(length, window, None, None)
+    a = np.zeros(max(P, 1), np.int32)
+    b = np.zeros(max(P, 1), np.int32)
+    L.orc_walk_offsets(length, window, a.ctypes.data, b.ctypes.data)
+    return a[:P], b[:P]
+
+
+def walk_order(n, P, seed, level=0, tag=0, epoch=0) -> np.ndarray:
+    out = np.zeros(max(n * P, 1), np.int64)
+    lib().orc_walk_order(n, P, seed, level, tag, epoch, out)
+    return out[:n * P]
+
+
+def walk_pairs(offsets, indices, length, window, seed, level=0, tag=0, epoch=0):
+    """The (source, positive) pairs of one epoch in visiting order (-1 for void)."""
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    m = n * len(walk_offsets(length, window)[0])
+    src = np.zeros(max(m, 1), np.int32)
+    pos = np.zeros(max(m, 1), np.int32)
+    lib().orc_walk_pairs(offsets, indices, n, seed, level, tag, epoch, length, window, src, pos)
+    return src[:m], pos[:m]
+
+
+def train_walks(offsets, indices, M, epochs, lr, k, length, window, seed, level=0, tag=0) -> int:
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    if M.shape[0] != n:
+        raise ValueError("embedding rows != |V|")
+    if not 0 <= k <= 15:
+        raise ValueError("k out of range")
+    e = _emb(M)
+    return int(lib().orc_train_walks(offsets, indices, n, C.byref(e), epochs, lr, k, length, window, seed, level,
+                                     tag))

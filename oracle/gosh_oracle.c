@@ -182,20 +182,22 @@ static double row_get(const orc_emb* M, int64_t v, int32_t e)
  * counter's block field (0 for Algorithm 3; the opposite part of a
  * partitioned visit). */
 static uint32_t sr_bits_hi(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
-                           int64_t src, uint32_t slot, int32_t e, int32_t d, uint32_t hi)
+                           int64_t src, uint32_t kind, uint32_t slot, int32_t e, int32_t d, uint32_t hi)
 {
     const int32_t L = d >= 8 ? d / 8 : 1;
     const int32_t w = e / 2;
     uint32_t out[4];
-    orc_stream_block(seed, level, tag, epoch, src, 1u, slot, (hi << 8) | (uint32_t)(w % L), out);
+    orc_stream_block(seed, level, tag, epoch, src, kind, slot, (hi << 8) | (uint32_t)(w % L), out);
     const int32_t h = 2 * (w / L) + (e % 2);
     const uint32_t word = out[h / 2];
     return (h & 1) ? (word >> 16) : (word & 0xFFFFu);
 }
 
-static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
-                        double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
-                        uint32_t hi)
+/* One visit (Algorithm 1 on each sample in turn).  BF16 rounding bits come
+ * from the stream (sid, epoch, kind sr_kind, slot, block hi << 8 | ...). */
+static int32_t visit_stream(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                            double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                            int64_t sid, uint32_t sr_kind, uint32_t hi)
 {
     const int32_t d = M->d;
     double* s = (double*)malloc(sizeof(double) * (size_t)d);
@@ -219,7 +221,7 @@ static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t
         for (int32_t e = 0; e < d; ++e) {
             double val = m[e] + s[e] * score;
             if (M->bf16) {
-                uint32_t r = sr_bits_hi(seed, level, tag, epoch, src, (uint32_t)t, e, d, hi);
+                uint32_t r = sr_bits_hi(seed, level, tag, epoch, sid, sr_kind, (uint32_t)t, e, d, hi);
                 ((uint16_t*)M->rows)[u * d + e] = orc_bf16_sr((float)val, r);
             } else {
                 ((double*)M->rows)[u * d + e] = val;
@@ -229,7 +231,7 @@ static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t
     }
     for (int32_t e = 0; e < d; ++e) {
         if (M->bf16) {
-            uint32_t r = sr_bits_hi(seed, level, tag, epoch, src, 0xFFu, e, d, hi);
+            uint32_t r = sr_bits_hi(seed, level, tag, epoch, sid, sr_kind, 0xFFu, e, d, hi);
             ((uint16_t*)M->rows)[src * d + e] = orc_bf16_sr((float)s[e], r);
         } else {
             ((double*)M->rows)[src * d + e] = s[e];
@@ -238,6 +240,13 @@ static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t
     free(s);
     free(m);
     return done;
+}
+
+static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                        double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                        uint32_t hi)
+{
+    return visit_stream(M, src, samples, k, lr, seed, level, tag, epoch, src, 1u, hi);
 }
 
 int32_t orc_visit(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
@@ -551,4 +560,133 @@ int64_t orc_train_partitioned(const int64_t* offsets, const int32_t* indices, in
     free(starts);
     free(pairs);
     return updates;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random-walk sampling (Section 3.2)                                       */
+/* ------------------------------------------------------------------------ */
+int32_t orc_walk(const int64_t* offsets, const int32_t* indices, uint64_t seed, int32_t level,
+                 uint32_t tag, int32_t epoch, int64_t v, int32_t len, int32_t* out)
+{
+    uint32_t w[4];
+    int64_t cur = v;
+    out[0] = (int32_t)v;
+    int32_t m = 1;
+    for (int32_t i = 0; i < len; ++i) {
+        if (i % 4 == 0)
+            orc_stream_block(seed, level, tag, epoch, v, 4u, 0u, (uint32_t)(i / 4), w);
+        const int64_t deg = offsets[cur + 1] - offsets[cur];
+        if (deg == 0)
+            break;
+        cur = indices[offsets[cur] + scale_word(w[i % 4], deg)];
+        out[m++] = (int32_t)cur;
+    }
+    return m;
+}
+
+int32_t orc_walk_offsets(int32_t len, int32_t window, int32_t* i_out, int32_t* j_out)
+{
+    int32_t P = 0;
+    for (int32_t i = 0; i < len; ++i)
+        for (int32_t j = i + 1; j <= len && j - i <= window; ++j) {
+            if (i_out) {
+                i_out[P] = i;
+                j_out[P] = j;
+            }
+            ++P;
+        }
+    return P;
+}
+
+typedef struct {
+    uint32_t key;
+    int64_t idx;
+} key_idx;
+
+static int cmp_key_idx(const void* a, const void* b)
+{
+    const key_idx* x = (const key_idx*)a;
+    const key_idx* y = (const key_idx*)b;
+    if (x->key != y->key)
+        return x->key < y->key ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+int64_t orc_walk_order(int64_t n, int32_t P, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                       int64_t* order_out)
+{
+    const int64_t m = n * (int64_t)P;
+    key_idx* kv = (key_idx*)malloc(sizeof(key_idx) * (size_t)(m > 0 ? m : 1));
+    for (int64_t q = 0; q < m; ++q) {
+        uint32_t w[4];
+        orc_stream_block(seed, level, tag, epoch, q, 5u, 0u, 0u, w);
+        kv[q].key = w[0];
+        kv[q].idx = q;
+    }
+    qsort(kv, (size_t)m, sizeof(key_idx), cmp_key_idx);
+    for (int64_t r = 0; r < m; ++r)
+        order_out[r] = kv[r].idx;
+    free(kv);
+    return m;
+}
+
+int64_t orc_walk_pairs(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,
+                       int32_t level, uint32_t tag, int32_t epoch, int32_t len, int32_t window,
+                       int32_t* src_out, int32_t* pos_out)
+{
+    const int32_t P = orc_walk_offsets(len, window, NULL, NULL);
+    const int64_t m = n * (int64_t)P;
+    int32_t* ti = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P > 0 ? P : 1));
+    int32_t* tj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P > 0 ? P : 1));
+    orc_walk_offsets(len, window, ti, tj);
+    /* every walk of the epoch, walk v in row v */
+    int32_t* walks = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)(len + 1));
+    int32_t* wlen = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t v = 0; v < n; ++v)
+        wlen[v] = orc_walk(offsets, indices, seed, level, tag, epoch, v, len, walks + v * (len + 1));
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    orc_walk_order(n, P, seed, level, tag, epoch, order);
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t v = order[r] / P;
+        const int32_t l = (int32_t)(order[r] % P);
+        const int void_pair = tj[l] >= wlen[v];
+        src_out[r] = void_pair ? -1 : walks[v * (len + 1) + ti[l]];
+        pos_out[r] = void_pair ? -1 : walks[v * (len + 1) + tj[l]];
+    }
+    free(order);
+    free(wlen);
+    free(walks);
+    free(tj);
+    free(ti);
+    return m;
+}
+
+int64_t orc_train_walks(const int64_t* offsets, const int32_t* indices, int64_t n, orc_emb* M,
+                        int32_t epochs, double lr, int32_t k, int32_t len, int32_t window,
+                        uint64_t seed, int32_t level, uint32_t tag)
+{
+    const int64_t m = n * (int64_t)orc_walk_offsets(len, window, NULL, NULL);
+    int32_t* src = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int64_t done = 0;
+    int32_t samples[64];
+    uint32_t w[64];
+    for (int32_t j = 0; j < epochs; ++j) {
+        const double f = 1.0 - (double)j / (double)epochs;
+        const double lrj = lr * (f > 1e-4 ? f : 1e-4);
+        orc_walk_pairs(offsets, indices, n, seed, level, tag, j, len, window, src, pos);
+        for (int64_t r = 0; r < m; ++r) {
+            if (src[r] < 0)
+                continue;
+            for (int32_t b = 0; 4 * b <= k; ++b)
+                orc_stream_block(seed, level, tag, j, r, 6u, 0u, (uint32_t)b, w + 4 * b);
+            samples[0] = pos[r];
+            for (int32_t t = 1; t <= k; ++t)
+                samples[t] = (int32_t)scale_word(w[t], n);
+            done += visit_stream(M, src[r], samples, k, lrj, seed, level, tag, j, r, 7u, 0u);
+        }
+    }
+    free(src);
+    free(pos);
+    return done;
 }

@@ -13,6 +13,7 @@
  *   - MultiEdgeCollapse .... Algorithm 4 (Section 4), CSR build (Section 4.1)
  *   - epoch distribution ... Section 3 (calculateEpochs of Algorithm 2)
  *   - partitioned embedding  Section 5 (parts, inside-out order, sample pools)
+ *   - random-walk sampling . Section 3.2
  * Philox4x32-10 follows Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers:
  * As Easy as 1, 2, 3", SC'11.
  */
@@ -128,6 +129,37 @@ int64_t orc_train_partitioned(const int64_t* offsets, const int32_t* indices, in
                               orc_emb* M, int32_t K, int32_t B, int32_t epochs, double lr,
                               int32_t k, uint64_t seed, int32_t level, uint32_t tag,
                               int64_t* positives_out);
+
+/* ---- Random-walk sampling (Section 3.2) ---------------------------------
+ * Epoch j starts one walk of `len` steps at every vertex v: w_0 = v and
+ * w_{i+1} = neighbour floor(r deg / 2^32) of w_i, r = word i mod 4 of the
+ * stream (v, j, kind 4, block i div 4); a walk stops at a vertex without
+ * neighbours.  Every pair (w_a, w_b) with 0 < b - a <= window is a positive
+ * sample with source w_a.  The P pair offsets (a, b), 0 <= a < b <= len,
+ * b - a <= window, are numbered by a, then b; pair q = v P + l is offset l
+ * of walk v and is void when b is past the end of walk v.  The epoch visits
+ * the n P pairs in the order of the key word 0 of (q, j, kind 5), ties by q.
+ * The pair at rank r (void ones keep their rank and are not visited) draws
+ * its k negatives uniformly over [0, n) from words 1..k of (r, j, kind 6)
+ * and is visited like a source of Algorithm 3, with lr' = lr max(1 - j/e,
+ * 1e-4), a positive or negative equal to the source skipped, and BF16
+ * rounding bits from (r, j, kind 7, slot, block) laid out as for kind 1. */
+int32_t orc_walk(const int64_t* offsets, const int32_t* indices, uint64_t seed, int32_t level,
+                 uint32_t tag, int32_t epoch, int64_t v, int32_t len, int32_t* out);
+/* P, and the offsets (a in i_out, b in j_out; may be NULL). */
+int32_t orc_walk_offsets(int32_t len, int32_t window, int32_t* i_out, int32_t* j_out);
+/* The visiting order of the epoch's n P pair indices. */
+int64_t orc_walk_order(int64_t n, int32_t P, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                       int64_t* order_out);
+/* The epoch's pairs in visiting order (src_out/pos_out[n P]; -1 for void). */
+int64_t orc_walk_pairs(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,
+                       int32_t level, uint32_t tag, int32_t epoch, int32_t len, int32_t window,
+                       int32_t* src_out, int32_t* pos_out);
+/* `epochs` epochs of walk-sampled training; returns the executed UpdateEmbed
+ * calls. */
+int64_t orc_train_walks(const int64_t* offsets, const int32_t* indices, int64_t n, orc_emb* M,
+                        int32_t epochs, double lr, int32_t k, int32_t len, int32_t window,
+                        uint64_t seed, int32_t level, uint32_t tag);
 
 #ifdef __cplusplus
 }
