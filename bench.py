@@ -72,7 +72,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22", "rmat26"])
+    ap.add_argument("--workload", default="rmat20",
+                    choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22", "rmat26", "walk20"])
+    ap.add_argument("--walk-len", type=int, default=10, help="walk length of the walk20 workload")
+    ap.add_argument("--walk-window", type=int, default=3, help="sampling distance of the walk20 workload")
+    ap.add_argument("--walk-epochs", type=int, default=24, help="walk epochs over all levels (walk20)")
     ap.add_argument("--big-scale", type=int, default=26, help="R-MAT scale of the rmat26 workload")
     ap.add_argument("--big-ef", type=float, default=28, help="R-MAT edge factor of the rmat26 workload")
     ap.add_argument("--big-cap-gib", type=float, default=16, help="device-memory cap of the partitioned leg")
@@ -514,6 +518,100 @@ def big_workload(a):
     print(json.dumps(out), flush=True)
 
 
+def walk_workload(a):
+    """Random-walk sampling (Section 3.2) in the multi-level pass: the scale-20
+    R-MAT train graph of the default workload, d = 128, k = 3, one walk of
+    --walk-len steps per vertex and epoch with every pair within --walk-window
+    steps a positive (P = 27 pairs per walk by default), --walk-epochs epochs
+    over all levels (p = 0.3), BF16 rows.  A step is coarsening, walk-sampled
+    training of every level and copy prolongation.  value = executed
+    UpdateEmbed calls per second of step wall time.  roofline: the level-0
+    update launch (k_walk_train); algorithmic bytes per pair 2*d*b*(2+k) + 12
+    (rows as in the per-epoch trainer, the 4-byte order entry and the two
+    4-byte walk entries), its duration from the library's events around the
+    level-0 update launches inside the timed steps.  cpu_baseline: one epoch
+    of the FP64 walk trainer on the scale-18 train graph of the same recipe."""
+    import torch
+
+    import oracle
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    from synth import evaluate_auc, init_rows, rmat_csr, split_edges
+
+    scale, ef, d, k, threshold, p, lr = 20, 16, 128, 3, 100, 0.3, 0.045
+    L, W, E = a.walk_len, a.walk_window, a.walk_epochs
+    seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4, "eval": 5}
+    t0 = time.time()
+    sp = split_edges(*rmat_csr(scale, ef, seeds["graph"]), seeds["split"])
+    n0, nnz = sp.n, len(sp.indices)
+    log(f"graph ready: |V_train|={n0} nnz={nnz} ({time.time() - t0:.1f}s)")
+    ctx = G.Context(0, seed=seeds["philox"])
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    G.gosh_validate_csr(ctx, g, check_symmetry=True)
+    cfg = EmbedConfig(d=d, epochs=E, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=threshold,
+                      sampler="walk", walk_len=L, window=W)
+    lv = G.gosh_coarsen(ctx, g, threshold)
+    n_c = lv.sizes()[-1]
+    init_dev = torch.from_numpy(init_rows(n_c, d, seeds["init"])).cuda().to(torch.bfloat16)
+    del lv
+
+    def init_fn(nn, dd):
+        return init_dev.clone()
+
+    for _ in range(a.warmup):
+        embed(ctx, g, cfg, init_fn)
+    torch.cuda.synchronize()
+    results = []
+    t = time.perf_counter()
+    for _ in range(a.steps):
+        results.append(embed(ctx, g, cfg, init_fn, level_events=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    updates = sum(int(r.updates.item()) for r in results)
+    last = results[-1]
+    e0 = last.schedule[0]
+    P = min(W, L) * L - min(W, L) * (min(W, L) - 1) // 2
+    iso = int(np.count_nonzero(np.diff(sp.offsets) == 0))
+    pairs0 = (n0 - iso) * P
+    train_ms = float(np.mean([r.timings["walk_level0"]["train_ms"] for r in results]))
+    sample_ms = float(np.mean([r.timings["walk_level0"]["sample_ms"] for r in results]))
+    launch_s = train_ms / 1e3 / e0
+    per_pair = 2 * d * 2 * (2 + k) + 12
+    ach = pairs0 * per_pair / launch_s / 1e9
+    log(f"walk: {1e3 * wall / a.steps:.2f} ms/step, {updates / wall / 1e9:.3f} G edge-samples/s, level-0 "
+        f"update launch {launch_s * 1e6:.1f} us, sampling {sample_ms / e0:.2f} ms/epoch, levels {last.sizes}")
+    out = {
+        "metric": "edge-samples/s (executed UpdateEmbed calls) of the whole hot path with random-walk sampling",
+        "value": round(updates / wall, 1), "unit": "edge-samples/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * wall / a.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {scale} ef {ef} link-prediction train graph (|V|={n0}, nnz={nnz}), "
+                               f"d={d}, k={k}, walk length {L}, window {W} ({P} pairs per walk), {E} walk epochs, "
+                               f"p={p}, lr={lr}, threshold={threshold}, BF16 rows + SR",
+                   "levels": last.sizes, "schedule": last.schedule, "seeds": seeds,
+                   "updates_per_step": updates // a.steps},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_walk_train level 0",
+                     "bytes_per_launch": pairs0 * per_pair, "launch_us": round(launch_s * 1e6, 2)},
+        "level0_sampling_ms_per_epoch": round(sample_ms / e0, 3),
+    }
+    if not a.no_auc:
+        out["auc"] = {"bf16": round(evaluate_auc(last.emb.float().cpu().numpy(), sp, seeds["eval"],
+                                                 max_train=200_000), 4)}
+        log(f"auc {out['auc']}")
+    if not a.no_cpu_baseline:
+        small = split_edges(*rmat_csr(18, ef, seeds["graph"]), seeds["split"])
+        M = init_rows(small.n, d, seeds["init"]).astype(np.float64)
+        t = time.perf_counter()
+        upd = oracle.train_walks(small.offsets, small.indices, M, 1, lr, k, L, W, seeds["philox"])
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(upd / dt, 1), "unit": "edge-samples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 sequential walk trainer, 1 epoch over the scale-18 train graph of "
+                                         f"the same recipe ({small.n} walks, {upd} updates, {dt:.1f} s)"}
+        log(f"cpu baseline {upd / dt / 1e6:.2f} M edge-samples/s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -527,6 +625,8 @@ def main():
         return partition_workload(a)
     if a.workload == "rmat26":
         return big_workload(a)
+    if a.workload == "walk20":
+        return walk_workload(a)
     import torch
 
     from paper_2110_10049_amd import gosh as G

@@ -171,6 +171,50 @@ gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void
                        gosh_dtype dt, int32_t d, int32_t epochs, float lr, int32_t k,
                        uint32_t tag, uint64_t* updates_dev);
 
+/* Random-walk positive sampling (Section 3.2) on level `level` of `lv`, in
+ * place of the one-neighbour positives of gosh_train: epoch j starts one
+ * walk of `walk_len` steps at every vertex v (w_0 = v; step i picks the
+ * neighbour floor(r deg / 2^32) of the current vertex with r = word i mod 4
+ * of the stream (v, j, kind 4, block i div 4); a walk stops early at a
+ * vertex without neighbours).  Every pair (w_a, w_b) with
+ * 0 < b - a <= window is a positive sample with source w_a.  With P the
+ * number of offsets (a, b), 0 <= a < b <= walk_len, b - a <= window, taken in
+ * order of a then b, pair q = v P + l is offset l of walk v; the epoch visits
+ * the n P pairs sorted by the key word 0 of stream (q, j, kind 5), ties by q
+ * (a shuffle of the epoch's samples).  The pair at rank r draws k negatives
+ * uniformly over the level's vertices from words 1..k of stream (r, j,
+ * kind 6) and applies UpdateEmbed (Algorithm 1) as gosh_train does, with
+ * lr' = lr * max(1 - j/epochs, 1e-4), a sample equal to its source skipped
+ * and BF16 rounding bits from stream (r, j, kind 7, slot, block) laid out as
+ * for kind 1.  Pairs past the end of a shortened walk are skipped.  Pairs of
+ * an epoch run concurrently with atomic row updates (as gosh_train); in
+ * deterministic mode they run one at a time in rank order.
+ * 0 <= walk_len <= 1024, window >= 0; n * P must be below 2^32
+ * (GOSH_E_UNSUPPORTED otherwise).  Device memory: 4 n (walk_len + 1) +
+ * 16 n P bytes of scratch for the walks and the shuffle, taken from the
+ * context (GOSH_E_CAP_EXCEEDED under its cap).  Other arguments and errors
+ * as gosh_train.  Asynchronous when timing_host is NULL; otherwise the call
+ * waits for its work and fills *timing_host. */
+typedef struct {
+    double sample_ms;   /* device time of the walks, shuffle keys and sort, all epochs */
+    double train_ms;    /* device time of the update launches, all epochs             */
+    int32_t epochs;     /* epochs run                                                 */
+} gosh_walk_timing;
+
+gosh_status gosh_train_walks(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void* emb,
+                             gosh_dtype dt, int32_t d, int32_t epochs, float lr, int32_t k,
+                             int32_t walk_len, int32_t window, uint32_t tag, uint64_t* updates_dev,
+                             gosh_walk_timing* timing_host);
+
+/* The positive pairs of epoch `epoch` of gosh_train_walks in visiting order:
+ * src_dev[r], pos_dev[r] for the pair at rank r (both -1 for a pair past the
+ * end of its walk).  *count receives n P.  With src_dev and pos_dev both NULL
+ * only *count is set; otherwise both must hold `capacity` >= n P entries
+ * (GOSH_E_INVALID_ARG).  Asynchronous. */
+gosh_status gosh_walk_pairs(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, int32_t epoch,
+                            int32_t walk_len, int32_t window, uint32_t tag, int32_t* src_dev,
+                            int32_t* pos_dev, int64_t capacity, int64_t* count);
+
 /* One independent training job of gosh_train_batched. */
 typedef struct {
     gosh_csr g;          /* the job's graph (device, borrowed; must satisfy the graph

@@ -87,6 +87,8 @@ def lib():
         L.orc_walk.restype = C.c_int32
         L.orc_walk_offsets.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         L.orc_walk_offsets.restype = C.c_int32
+        L.orc_walk_keys.argtypes = [C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, _u32p]
+        L.orc_walk_keys.restype = None
         L.orc_walk_order.argtypes = [C.c_int64, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, _i64p]
         L.orc_walk_order.restype = C.c_int64
         L.orc_walk_pairs.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32,
@@ -347,6 +349,13 @@ def walk_offsets(length, window):
     b = np.zeros(max(P, 1), np.int32)
     L.orc_walk_offsets(length, window, a.ctypes.data, b.ctypes.data)
     return a[:P], b[:P]
+
+
+def walk_keys(m, seed, level=0, tag=0, epoch=0) -> np.ndarray:
+    """Shuffle keys of pair numbers 0..m-1."""
+    out = np.zeros(max(m, 1), np.uint32)
+    lib().orc_walk_keys(m, seed, level, tag, epoch, out)
+    return out[:m]
 
 
 def walk_order(n, P, seed, level=0, tag=0, epoch=0) -> np.ndarray:

@@ -612,6 +612,15 @@ static int cmp_key_idx(const void* a, const void* b)
     return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
+void orc_walk_keys(int64_t m, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch, uint32_t* keys_out)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        uint32_t w[4];
+        orc_stream_block(seed, level, tag, epoch, q, 5u, 0u, 0u, w);
+        keys_out[q] = w[0];
+    }
+}
+
 int64_t orc_walk_order(int64_t n, int32_t P, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
                        int64_t* order_out)
 {

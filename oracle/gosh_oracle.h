@@ -148,6 +148,8 @@ int32_t orc_walk(const int64_t* offsets, const int32_t* indices, uint64_t seed, 
                  uint32_t tag, int32_t epoch, int64_t v, int32_t len, int32_t* out);
 /* P, and the offsets (a in i_out, b in j_out; may be NULL). */
 int32_t orc_walk_offsets(int32_t len, int32_t window, int32_t* i_out, int32_t* j_out);
+/* The shuffle keys of pair numbers 0..m-1. */
+void orc_walk_keys(int64_t m, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch, uint32_t* keys_out);
 /* The visiting order of the epoch's n P pair indices. */
 int64_t orc_walk_order(int64_t n, int32_t P, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
                        int64_t* order_out);

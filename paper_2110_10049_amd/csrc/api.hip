@@ -413,6 +413,30 @@ gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void
     });
 }
 
+gosh_status gosh_train_walks(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void* emb, gosh_dtype dt,
+                             int32_t d, int32_t epochs, float lr, int32_t k, int32_t walk_len, int32_t window,
+                             uint32_t tag, uint64_t* updates_dev, gosh_walk_timing* timing_host) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        const gosh::Level& L = level_of(lv, level);
+        set_device(&ctx->c);
+        gosh::train_walks(&ctx->c, L, level, emb, dt, d, epochs, lr, k, walk_len, window, tag, updates_dev,
+                          timing_host);
+    });
+}
+
+gosh_status gosh_walk_pairs(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, int32_t epoch, int32_t walk_len,
+                            int32_t window, uint32_t tag, int32_t* src_dev, int32_t* pos_dev, int64_t capacity,
+                            int64_t* count) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        GOSH_REQUIRE(count, GOSH_E_INVALID_ARG, "null count");
+        const gosh::Level& L = level_of(lv, level);
+        set_device(&ctx->c);
+        *count = gosh::walk_pairs(&ctx->c, L, level, epoch, walk_len, window, tag, src_dev, pos_dev, capacity);
+    });
+}
+
 gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs, gosh_dtype dt, int32_t d,
                                int32_t k, gosh_batch_mode mode, uint64_t* updates_dev, int32_t* chosen_out) {
     if (!ctx) return GOSH_E_INVALID_ARG;

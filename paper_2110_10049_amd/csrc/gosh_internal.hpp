@@ -174,6 +174,13 @@ int64_t partition_pool(const gosh_csr* g, int K, int i, int j, int B, uint64_t s
                        uint32_t tag, int32_t round, int threads, int32_t* src, int32_t* pos, int32_t* b,
                        int64_t capacity);
 void inside_out_pairs(int K, int32_t* out);
+// (walk.hip)
+int64_t walk_pair_count(int32_t len, int32_t window);
+void train_walks(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d, int epochs, float lr,
+                 int k, int32_t len, int32_t window, uint32_t tag, uint64_t* updates_dev,
+                 gosh_walk_timing* timing);
+int64_t walk_pairs(Ctx* c, const Level& L, int32_t level, int32_t epoch, int32_t len, int32_t window, uint32_t tag,
+                   int32_t* src, int32_t* pos, int64_t capacity);
 // (mlp.hip)
 gosh_mlp* mlp_create(gosh_ctx* owner, int d, int hidden);
 void mlp_free(gosh_mlp* M);

@@ -137,12 +137,103 @@ __device__ __forceinline__ float sigmoidf_(float x) {
     return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
 }
 
+// UpdateEmbed (Algorithm 1) on samples u[0..k] of one source, u[0] the
+// positive: the source row is updated in registers along the chain and
+// written back once at the end.  Samples that are -1 or equal to the source
+// are skipped (a skipped negative is subtracted from `updates`, which the
+// callers precount).  BF16 rounding bits come from the stream (sid, epoch,
+// w2, kind sr_kind | slot t or 255 | block gl).  COH: loads bypass the
+// non-coherent caches (rows written by other waves of the same launch).
+template <bool BF16, int D, int KMAX, bool COH>
+__device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* M, int64_t src,
+                                             const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
+                                             uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t key0,
+                                             uint32_t key1, unsigned long long* updates, int gl) {
+    constexpr int L = D / kEPL;
+    using IO = RowIO<BF16>;
+    float s[kEPL];
+    float m[KMAX + 1][kEPL];
+    IO::template load<L, COH>(M, src, gl, s);
+#pragma unroll
+    for (int t = 0; t <= KMAX; ++t) {
+        if (u[t] >= 0 && u[t] != src) {
+            IO::template load<L, COH>(M, u[t], gl, m[t]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) m[t][e] = 0.0f;
+        }
+    }
+
+    int done = 0;
+    float s0[kEPL];
+#pragma unroll
+    for (int e = 0; e < kEPL; ++e) s0[e] = s[e];
+#pragma unroll
+    for (int t = 0; t <= KMAX; ++t) {
+        if (t > k) break;
+        const int32_t ut = u[t];
+        if (ut < 0 || ut == src) {
+            if (t > 0 && ut == src && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
+            continue;
+        }
+        // a row sampled earlier in this visit continues from its updated value
+#pragma unroll
+        for (int tp = 0; tp < t; ++tp) {
+            if (u[tp] == ut) {
+#pragma unroll
+                for (int e = 0; e < kEPL; ++e) m[t][e] = m[tp][e];
+            }
+        }
+        float x = 0.0f;
+#pragma unroll
+        for (int e = 0; e < kEPL; ++e) x = fmaf(s[e], m[t][e], x);
+        x = group_sum<L>(x);
+        const float b = (t == 0) ? 1.0f : 0.0f;
+        const float g = (b - sigmoidf_(x)) * lr;
+#pragma unroll
+        for (int e = 0; e < kEPL; ++e) s[e] = fmaf(g, m[t][e], s[e]);
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(sid, epoch, w2,
+                                                   stream_word3(sr_kind, static_cast<uint32_t>(t),
+                                                                static_cast<uint32_t>(gl))),
+                                        key0, key1);
+            float v[kEPL], out[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) v[e] = fmaf(g, s[e], m[t][e]);
+            IO::template commit<L>(M, ut, gl, m[t], v, bits, out);
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) m[t][e] = out[e];
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) {
+                dx[e] = g * s[e];
+                m[t][e] += dx[e];
+            }
+            IO::template add<L>(M, ut, gl, dx);
+        }
+        ++done;
+    }
+    if (done) {
+        if constexpr (BF16) {
+            const uint4 bits = philox10(make_uint4(sid, epoch, w2,
+                                                   stream_word3(sr_kind, 0xFFu, static_cast<uint32_t>(gl))),
+                                        key0, key1);
+            float out[kEPL];
+            IO::template commit<L>(M, src, gl, s0, s, bits, out);
+        } else {
+            float dx[kEPL];
+#pragma unroll
+            for (int e = 0; e < kEPL; ++e) dx[e] = s[e] - s0[e];
+            IO::template add<L>(M, src, gl, dx);
+        }
+    }
+}
+
 // One source visit: draws (or reads) the samples and applies the updates.
 template <bool BF16, int D, int KMAX, class Off, int MODE>
 __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool active, int gl) {
-    constexpr int L = D / kEPL;
-    using IO = RowIO<BF16>;
-    using Elem = typename IO::Elem;
+    using Elem = typename RowIO<BF16>::Elem;
     Elem* M = static_cast<Elem*>(P.emb);
     const int k = P.k;
 
@@ -194,86 +285,8 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
         }
     }
     if (!active) return;
-
-    float s[kEPL];
-    float m[KMAX + 1][kEPL];
-    constexpr bool kCoherent = (MODE == kPersistent);
-    IO::template load<L, kCoherent>(M, src, gl, s);
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (u[t] >= 0 && u[t] != src) {
-            IO::template load<L, kCoherent>(M, u[t], gl, m[t]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < kEPL; ++e) m[t][e] = 0.0f;
-        }
-    }
-
-    int done = 0;
-    const float lr = P.lr;
-    float s0[kEPL];
-#pragma unroll
-    for (int e = 0; e < kEPL; ++e) s0[e] = s[e];
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (t > k) break;
-        const int32_t ut = u[t];
-        if (ut < 0 || ut == src) {
-            if (t > 0 && ut == src && P.updates && gl == 0) atomicAdd(P.updates, ~0ull);  // -1
-            continue;
-        }
-        // a row sampled earlier in this visit continues from its updated value
-#pragma unroll
-        for (int tp = 0; tp < t; ++tp) {
-            if (u[tp] == ut) {
-#pragma unroll
-                for (int e = 0; e < kEPL; ++e) m[t][e] = m[tp][e];
-            }
-        }
-        float x = 0.0f;
-#pragma unroll
-        for (int e = 0; e < kEPL; ++e) x = fmaf(s[e], m[t][e], x);
-        x = group_sum<L>(x);
-        const float b = (t == 0) ? 1.0f : 0.0f;
-        const float g = (b - sigmoidf_(x)) * lr;
-#pragma unroll
-        for (int e = 0; e < kEPL; ++e) s[e] = fmaf(g, m[t][e], s[e]);
-        if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
-                                                   stream_word3(1, static_cast<uint32_t>(t),
-                                                                static_cast<uint32_t>(gl))),
-                                        P.key0, P.key1);
-            float v[kEPL], out[kEPL];
-#pragma unroll
-            for (int e = 0; e < kEPL; ++e) v[e] = fmaf(g, s[e], m[t][e]);
-            IO::template commit<L>(M, ut, gl, m[t], v, bits, out);
-#pragma unroll
-            for (int e = 0; e < kEPL; ++e) m[t][e] = out[e];
-        } else {
-            float dx[kEPL];
-#pragma unroll
-            for (int e = 0; e < kEPL; ++e) {
-                dx[e] = g * s[e];
-                m[t][e] += dx[e];
-            }
-            IO::template add<L>(M, ut, gl, dx);
-        }
-        ++done;
-    }
-    if (done) {
-        if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2,
-                                                   stream_word3(1, 0xFFu, static_cast<uint32_t>(gl))),
-                                        P.key0, P.key1);
-            float out[kEPL];
-            IO::template commit<L>(M, src, gl, s0, s, bits, out);
-        } else {
-            float dx[kEPL];
-#pragma unroll
-            for (int e = 0; e < kEPL; ++e) dx[e] = s[e] - s0[e];
-            IO::template add<L>(M, src, gl, dx);
-        }
-    }
+    update_chain<BF16, D, KMAX, MODE == kPersistent>(M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch,
+                                                     P.w2, 1u, P.key0, P.key1, P.updates, gl);
 }
 
 }  // namespace train_detail

@@ -28,6 +28,12 @@ class EmbedConfig:
     # (single persistent launch) path instead of one launch per epoch; 0 = off
     batch_levels_upto: int = 0
     batch_mode: int = G.GOSH_BATCH_AUTO
+    # positive sampling: "edge" (one uniform neighbour per source and epoch,
+    # Algorithm 3) or "walk" (every pair within `window` steps of one walk of
+    # `walk_len` steps per vertex and epoch, shuffled; Section 3.2)
+    sampler: str = "edge"
+    walk_len: int = 10
+    window: int = 3
 
 
 @dataclass
@@ -48,10 +54,14 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
     """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level.
 
     With level_events, timings["train_events"][i] holds a (start, end) pair
-    of events recorded on the context stream around level i's training.
+    of events recorded on the context stream around level i's training, and
+    with the walk sampler timings["walk_level0"] holds the device time of
+    level 0's sampling and update launches (the call waits for level 0).
     mlp: expand with the learned prolongation instead of the copy.
     keep_levels: keep every level's trained rows in result.trained (the
     (coarse, fine) pairs the prolongation network is trained on)."""
+    if cfg.sampler not in ("edge", "walk"):
+        raise ValueError(f"unknown sampler {cfg.sampler!r}")
     if levels is None:
         levels = G.gosh_coarsen(ctx, g0, cfg.threshold, cfg.max_ratio) if coarsen else G.gosh_levels_single(ctx, g0)
     D = levels.count()
@@ -63,12 +73,18 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
         raise ValueError("init_fn returned a wrong shape or dtype")
     counter = torch.zeros(1, dtype=torch.int64, device=dev)
     events = {}
+    events_walk = None
     trained = {}
     for i in range(D - 1, -1, -1):
         if level_events:
             ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             ev[0].record(ctx.stream)
-        if cfg.batch_levels_upto and sizes[i] <= cfg.batch_levels_upto:
+        if cfg.sampler == "walk":
+            tm = G.gosh_train_walks(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.walk_len, cfg.window, cfg.tag,
+                                    counter, timing=level_events and i == 0)
+            if tm is not None:
+                events_walk = tm
+        elif cfg.batch_levels_upto and sizes[i] <= cfg.batch_levels_upto:
             G.gosh_train_batched(ctx, [(levels.csr(i), M, sched[i], cfg.lr, i, cfg.tag)], cfg.k,
                                  cfg.batch_mode, updates=counter)
         else:
@@ -83,4 +99,4 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
             G.gosh_prolong(ctx, levels, i - 1, M, fine, mlp=mlp)
             M = fine
     return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels,
-                       timings={"train_events": events}, trained=trained)
+                       timings={"train_events": events, "walk_level0": events_walk}, trained=trained)

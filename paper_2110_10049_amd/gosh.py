@@ -27,6 +27,10 @@ class GoshError(RuntimeError):
         self.status = STATUS.get(code, str(code))
 
 
+class gosh_walk_timing(C.Structure):
+    _fields_ = [("sample_ms", C.c_double), ("train_ms", C.c_double), ("epochs", C.c_int32)]
+
+
 class gosh_csr(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("offsets", C.c_void_p),
                 ("offsets_is_i64", C.c_int32), ("indices", C.c_void_p)]
@@ -90,6 +94,10 @@ _SIGNATURES = [
     ("gosh_epoch_schedule", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     ("gosh_train", C.c_int, [_P, _P, C.c_int32, _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
                              C.c_int32, C.c_uint32, _P]),
+    ("gosh_train_walks", C.c_int, [_P, _P, C.c_int32, _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, C.POINTER(gosh_walk_timing)]),
+    ("gosh_walk_pairs", C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _P,
+                                  C.c_int64, C.POINTER(C.c_int64)]),
     ("gosh_train_batched", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
                                      C.c_int, _P, C.POINTER(C.c_int32)]),
     ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32, _P]),
@@ -313,6 +321,39 @@ def gosh_train(ctx: Context, lv: Levels, level: int, emb: torch.Tensor, epochs: 
     e = _dev(emb, name="emb")
     u = _dev(updates, torch.int64, "updates") if updates is not None else None
     ctx.check(lib().gosh_train(ctx.h, lv.h, level, e, _dtype_code(emb), emb.shape[1], epochs, lr, k, tag, u))
+
+
+def gosh_train_walks(ctx: Context, lv: Levels, level: int, emb: torch.Tensor, epochs: int, lr: float, k: int,
+                     walk_len: int, window: int, tag: int = 0, updates: torch.Tensor | None = None,
+                     timing: bool = False):
+    """Random-walk positive sampling (Section 3.2) on one level; see gosh.h.
+    With timing, waits and returns {"sample_ms", "train_ms", "epochs"}."""
+    n, _ = lv.shape(level)
+    if emb.dim() != 2 or emb.shape[0] != n:
+        raise ValueError(f"embedding must be [{n}, d]")
+    e = _dev(emb, name="emb")
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    t = gosh_walk_timing() if timing else None
+    ctx.check(lib().gosh_train_walks(ctx.h, lv.h, level, e, _dtype_code(emb), emb.shape[1], epochs, lr, k,
+                                     walk_len, window, tag, u, C.byref(t) if timing else None))
+    if timing:
+        return {"sample_ms": t.sample_ms, "train_ms": t.train_ms, "epochs": t.epochs}
+    return None
+
+
+def gosh_walk_pairs(ctx: Context, lv: Levels, level: int, epoch: int, walk_len: int, window: int,
+                    tag: int = 0) -> tuple[torch.Tensor, torch.Tensor]:
+    """The (source, positive) pairs of one walk epoch in visiting order (-1 for void)."""
+    cnt = C.c_int64()
+    ctx.check(lib().gosh_walk_pairs(ctx.h, lv.h, level, epoch, walk_len, window, tag, None, None, 0,
+                                    C.byref(cnt)))
+    m = cnt.value
+    dev = f"cuda:{ctx.device}"
+    src = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    pos = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    ctx.check(lib().gosh_walk_pairs(ctx.h, lv.h, level, epoch, walk_len, window, tag, _dev(src), _dev(pos), m,
+                                    C.byref(cnt)))
+    return src[:m], pos[:m]
 
 
 def gosh_prolong(ctx: Context, lv: Levels, fine_level: int, coarse: torch.Tensor, fine: torch.Tensor,
