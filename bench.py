@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat20",
                     choices=sorted(WORKLOADS) + ["batch512", "mlp", "part22", "rmat26", "walk20"])
+    ap.add_argument("--dim", type=int, default=0, help="override the embedding dimension of rmat20/rmat12")
     ap.add_argument("--walk-len", type=int, default=10, help="walk length of the walk20 workload")
     ap.add_argument("--walk-window", type=int, default=3, help="sampling distance of the walk20 workload")
     ap.add_argument("--walk-epochs", type=int, default=24, help="walk epochs over all levels (walk20)")
@@ -634,6 +635,8 @@ def main():
     from synth import evaluate_auc, init_rows, rmat_csr, split_edges
 
     scale, ef, d, k, epochs, threshold = WORKLOADS[a.workload]
+    if a.dim:
+        d = a.dim
     p, lr = 0.3, 0.045
     seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4, "eval": 5}
     t0 = time.time()
@@ -726,7 +729,7 @@ def main():
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
                    "updates_per_step": bf["updates_per_step"]},
-        "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" else None),
+        "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),
     }
     if f32 is not None:

@@ -128,8 +128,8 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 // made wave-uniform, so the whole wave always runs the same iteration.
 template <bool BF16, int D, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs A) {
-    constexpr int L = D / kEPL;
-    constexpr int G = 64 / L;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     const uint64_t one = lane == 0 ? 1ull : 0ull;
@@ -175,8 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs A) {
 
 template <bool BF16, int D, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_multi(MultiArgs A) {
-    constexpr int L = D / kEPL;
-    constexpr int G = 64 / L;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     const int64_t slot = (static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6)) * G + grp;
@@ -215,12 +215,13 @@ __global__ void k_add_job_updates(const BJob* jobs, int k, unsigned long long* u
 struct Kernels {
     const void* persist;
     const void* multi;
+    int per_wave;      // sources per wave
 };
 
 template <bool BF16, int D, int KMAX>
 Kernels kernels_for() {
     return Kernels{reinterpret_cast<const void*>(&k_persist<BF16, D, KMAX>),
-                   reinterpret_cast<const void*>(&k_multi<BF16, D, KMAX>)};
+                   reinterpret_cast<const void*>(&k_multi<BF16, D, KMAX>), Lanes<BF16, D>::kG};
 }
 
 template <bool BF16, int D>
@@ -241,11 +242,9 @@ Kernels pick_d(int d, int k) {
         case 128: return pick_k<BF16, 128>(k);
         case 256: return pick_k<BF16, 256>(k);
     }
-    return Kernels{nullptr, nullptr};
+    return Kernels{nullptr, nullptr, 0};
 }
 
-int sources_per_iteration(int d) { return (kBlock / 64) * (64 / (d / kEPL)); }
-int sources_per_wave(int d) { return 64 / (d / kEPL); }
 
 // Device-side description of one batched call.
 struct Plan {
@@ -311,7 +310,7 @@ void run(Ctx* c, Plan& P, const RunShape& R, const Kernels& K, int d, int k, int
     }
     const uint32_t key0 = static_cast<uint32_t>(c->seed), key1 = static_cast<uint32_t>(c->seed >> 32);
     if (R.mode == GOSH_BATCH_PERSISTENT) {
-        const int64_t chunk = static_cast<int64_t>(sources_per_wave(d)) * R.chunk_iters;
+        const int64_t chunk = static_cast<int64_t>(K.per_wave) * R.chunk_iters;
         std::vector<int64_t> task0(njobs + 1, 0);
         for (int i = 0; i < njobs; ++i) {
             jobs[i].nchunks = ceil_div(jobs[i].n, chunk);
@@ -357,7 +356,7 @@ void run(Ctx* c, Plan& P, const RunShape& R, const Kernels& K, int d, int k, int
     } else {
         DevBuf<BJob> dj(c, njobs);
         GOSH_HIP(hipMemcpyAsync(dj.p, jobs.data(), sizeof(BJob) * njobs, hipMemcpyHostToDevice, c->stream));
-        const int per_block = sources_per_iteration(d);
+        const int per_block = (kBlock / 64) * K.per_wave;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         GOSH_HIP(hipGraphCreate(&graph, 0));

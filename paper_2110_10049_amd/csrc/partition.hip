@@ -68,9 +68,7 @@ struct PairArgs {
 
 template <bool BF16, int D, int KMAX>
 __device__ __forceinline__ void pair_visit(const PairArgs& P, int64_t e, int gl) {
-    constexpr int L = D / kEPL;
-    using IO = RowIO<BF16>;
-    using Elem = typename IO::Elem;
+    using Elem = typename RowIO<BF16>::Elem;
     const int k = P.k;
     const bool side1 = e >= P.n0;
     Elem* Ms = static_cast<Elem*>(side1 ? P.bin_b : P.bin_a);
@@ -102,94 +100,18 @@ __device__ __forceinline__ void pair_visit(const PairArgs& P, int64_t e, int gl)
 #pragma unroll
         for (int t = 1; t <= KMAX; ++t) u[t] = (t <= k) ? static_cast<int32_t>(scale_u32(wd[t], size_o)) : -1;
     }
-    // a sample that is the source itself (only possible when both parts coincide) is skipped
-    bool skip[KMAX + 1];
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) skip[t] = (t > k) || (start_o + u[t] == src_g);
-
-    float s[kEPL];
-    float m[KMAX + 1][kEPL];
-    IO::template load<L, false>(Ms, src, gl, s);
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (!skip[t]) {
-            IO::template load<L, false>(Mo, u[t], gl, m[t]);
-        } else {
-#pragma unroll
-            for (int x = 0; x < kEPL; ++x) m[t][x] = 0.0f;
-        }
-    }
-    const float lr = P.lr;
-    float s0[kEPL];
-#pragma unroll
-    for (int x = 0; x < kEPL; ++x) s0[x] = s[x];
-    int done = 0;
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (t > k) break;
-        if (skip[t]) {
-            if (P.updates && gl == 0) atomicAdd(P.updates, ~0ull);   // -1: counted in advance
-            continue;
-        }
-        const int32_t ut = u[t];
-#pragma unroll
-        for (int tp = 0; tp < t; ++tp) {
-            if (!skip[tp] && u[tp] == ut) {
-#pragma unroll
-                for (int x = 0; x < kEPL; ++x) m[t][x] = m[tp][x];
-            }
-        }
-        float dot = 0.0f;
-#pragma unroll
-        for (int x = 0; x < kEPL; ++x) dot = fmaf(s[x], m[t][x], dot);
-        dot = group_sum<L>(dot);
-        const float b = (t == 0) ? 1.0f : 0.0f;
-        const float g = (b - sigmoidf_(dot)) * lr;
-#pragma unroll
-        for (int x = 0; x < kEPL; ++x) s[x] = fmaf(g, m[t][x], s[x]);
-        if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src_g), eps, P.w2,
-                                                   stream_word3(1, static_cast<uint32_t>(t),
-                                                                (opp << 8) | static_cast<uint32_t>(gl))),
-                                        P.key0, P.key1);
-            float v[kEPL], out[kEPL];
-#pragma unroll
-            for (int x = 0; x < kEPL; ++x) v[x] = fmaf(g, s[x], m[t][x]);
-            IO::template commit<L>(Mo, ut, gl, m[t], v, bits, out);
-#pragma unroll
-            for (int x = 0; x < kEPL; ++x) m[t][x] = out[x];
-        } else {
-            float dx[kEPL];
-#pragma unroll
-            for (int x = 0; x < kEPL; ++x) {
-                dx[x] = g * s[x];
-                m[t][x] += dx[x];
-            }
-            IO::template add<L>(Mo, ut, gl, dx);
-        }
-        ++done;
-    }
-    if (done) {
-        if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(static_cast<uint32_t>(src_g), eps, P.w2,
-                                                   stream_word3(1, 0xFFu, (opp << 8) | static_cast<uint32_t>(gl))),
-                                        P.key0, P.key1);
-            float out[kEPL];
-            IO::template commit<L>(Ms, src, gl, s0, s, bits, out);
-        } else {
-            float dx[kEPL];
-#pragma unroll
-            for (int x = 0; x < kEPL; ++x) dx[x] = s[x] - s0[x];
-            IO::template add<L>(Ms, src, gl, dx);
-        }
-    }
+    // a sample that is the source itself (only possible when both parts
+    // coincide) is skipped
+    const int64_t self = (src_g >= start_o && src_g < start_o + size_o) ? src_g - start_o : -1;
+    update_chain<BF16, D, KMAX, false>(Ms, src, Mo, self, u, k, P.lr, static_cast<uint32_t>(src_g), eps, P.w2, 1u,
+                                       opp, P.key0, P.key1, P.updates, gl);
 }
 
 // SEQ: one wave walks the entries in pool order (deterministic mode).
 template <bool BF16, int D, int KMAX, bool SEQ>
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs P) {
-    constexpr int L = D / kEPL;
-    constexpr int G = 64 / L;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     const int64_t total = P.n0 + P.n1;
@@ -222,7 +144,7 @@ using PairLauncher = void (*)(const PairArgs&, hipStream_t, bool);
 
 template <bool BF16, int D, int KMAX>
 void launch_pair(const PairArgs& P, hipStream_t st, bool seq) {
-    constexpr int G = 64 / (D / kEPL);
+    constexpr int G = Lanes<BF16, D>::kG;
     if (seq) {
         hipLaunchKernelGGL((k_pair<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, P);
     } else {

@@ -1,12 +1,12 @@
 // TrainInGPU (Algorithm 3, Section 3.1) with UpdateEmbed (Algorithm 1) for
 // gfx950.
 //
-// Layout: every lane owns 8 elements of a row, so a source with dimension d
-// is served by a group of L = d/8 lanes and one wave64 carries 64/L sources
-// (d=128: 4 sources per wave, d=32: 16); the elements are interleaved across
-// the group (see RowIO) so that each memory instruction covers contiguous
-// bytes.  The dot product is reduced inside
-// the group with DPP (no LDS round trip).  Each group draws its samples from
+// Layout: a source is served by a group of L lanes (Lanes in visit.hpp: up
+// to 16 lanes, d/8 for d = 256), one wave64 carries 64/L sources (BF16:
+// d=128 4 sources per wave, d=8 16), and the row's 32-bit words are
+// interleaved across the group so that each memory instruction covers
+// contiguous bytes.  The dot product is reduced inside the group with DPP
+// (no LDS round trip).  Each group draws its samples from
 // Philox, issues the loads of the source row and of all 1+k sample rows at
 // once, then runs the dependent chain of updates from registers; the source
 // row plays the role of the paper's shared-memory staged row (Section 3.1),
@@ -21,7 +21,7 @@
 // written row is stochastically rounded with Philox bits (kind 1, slot =
 // update index or 255 for the source write-back): element e lies in 32-bit
 // word w = e/2, which draws block w mod L and takes half 2*(w div L) + e mod 2,
-// so lane gl draws exactly one block (block gl) per row update.
+// so lane gl draws exactly one block (block gl mod d/8) per row update.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,8 +39,8 @@ using namespace train_detail;
 
 template <bool BF16, int D, int KMAX, class Off, int MODE>
 __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
-    constexpr int L = D / kEPL;
-    constexpr int G = 64 / L;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     if constexpr (MODE == kSequential) {
@@ -113,7 +113,7 @@ using Launcher = void (*)(const TrainParams&, int64_t, hipStream_t);
 
 template <bool BF16, int D, int KMAX, class Off, int MODE>
 void launch(const TrainParams& P, int64_t items, hipStream_t st) {
-    constexpr int G = 64 / (D / kEPL);
+    constexpr int G = Lanes<BF16, D>::kG;
     if constexpr (MODE == kSequential) {
         hipLaunchKernelGGL((k_train<BF16, D, KMAX, Off, MODE>), dim3(1), dim3(64), 0, st, P);
     } else {

@@ -1,6 +1,7 @@
 // Per-source visit of TrainInGPU (Algorithm 3) with UpdateEmbed (Algorithm 1)
-// for gfx950, shared by the per-epoch trainer and the batched trainer.  See
-// train.hip for the lane layout and the write discipline.
+// for gfx950: the row layout, the row access with its write discipline and
+// the update chain shared by the per-epoch, batched, partitioned and
+// random-walk trainers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,7 +14,6 @@ namespace gosh {
 namespace train_detail {
 
 
-constexpr int kEPL = 8;       // row elements per lane
 constexpr int kBlock = 256;   // 4 waves
 
 struct TrainParams {
@@ -41,10 +41,29 @@ struct TrainParams {
 
 enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
 
-// Row access.  A lane of the group of L = d/8 lanes owns row elements
-// gl + L*i (FP32) or 32-bit words gl + L*i (BF16, two elements each), so
-// every load and every atomic instruction of a group covers one contiguous
-// run of the row.
+// Lane layout of a d-wide row.  A group of L lanes serves one row; lane gl
+// owns the 32-bit words gl + L*i, i < WPL (FP32: one element per word, BF16:
+// two), so every load and atomic instruction of a group covers one contiguous
+// run of L words.  The L2 atomic units take at most 64 bytes of a wave
+// instruction per request and sustain about 20 G requests/s next to about
+// 330 G atomic words/s, so a row is split over up to 16 lanes: rows of at
+// most 16 words take a single request per update (d = 8, 16, 32 in BF16),
+// wider rows stay at the word limit.  L is also a multiple of d/8, the number
+// of 4-word Philox blocks of a row's rounding bits, so every lane draws one
+// block per row update.
+template <bool BF16, int D>
+struct Lanes {
+    static constexpr int kWords = BF16 ? D / 2 : D;          // 32-bit words per row
+    static constexpr int kWide = D / 8 > 16 ? D / 8 : 16;
+    static constexpr int kL = kWords < kWide ? kWords : kWide;  // lanes per row
+    static constexpr int kWPL = kWords / kL;                  // words per lane
+    static constexpr int kEPL = BF16 ? 2 * kWPL : kWPL;       // elements per lane
+    static constexpr int kG = 64 / kL;                        // rows (sources) per wave
+    static constexpr int kBlocks = D / 8;                     // Philox blocks of rounding bits
+    static_assert(kL * kWPL == kWords && kL % kBlocks == 0 && 64 % kL == 0, "row layout");
+};
+
+// Row access.
 //
 // Writes are atomic: sources of an epoch run concurrently and share rows, and
 // a plain read-modify-write store would drop every concurrent update but the
@@ -57,19 +76,19 @@ enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
 // itself a BF16 value); contended, the concurrent changes add up in value
 // space.  (Adding bit-pattern differences with integer atomics would be
 // faster but wraps through the sign when many concurrent updates move one
-// element across zero.)  The L2 atomic units sustain about half the
-// bandwidth of plain stores, so they bound the training kernel.
+// element across zero.)  The L2 atomic units bound the training kernel.
 template <bool BF16>
 struct RowIO;
 
 template <>
 struct RowIO<false> {
     using Elem = float;
-    template <int L, bool COH>
-    __device__ static void load(const float* M, int64_t row, int gl, float (&x)[kEPL]) {
-        const float* p = M + row * (L * kEPL) + gl;
+    template <int D, bool COH>
+    __device__ static void load(const float* M, int64_t row, int gl, float (&x)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        const float* p = M + row * D + gl;
 #pragma unroll
-        for (int i = 0; i < kEPL; ++i) {
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i) {
             if constexpr (COH)
                 x[i] = __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p + L * i),
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -77,11 +96,12 @@ struct RowIO<false> {
                 x[i] = p[L * i];
         }
     }
-    template <int L>
-    __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[kEPL]) {
-        float* p = M + row * (L * kEPL) + gl;
+    template <int D>
+    __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        float* p = M + row * D + gl;
 #pragma unroll
-        for (int i = 0; i < kEPL; ++i)
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i)
             __hip_atomic_fetch_add(p + L * i, dx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
@@ -96,11 +116,12 @@ __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
 template <>
 struct RowIO<true> {
     using Elem = uint16_t;
-    template <int L, bool COH>
-    __device__ static void load(const uint16_t* M, int64_t row, int gl, float (&x)[kEPL]) {
-        const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * (L * kEPL)) + gl;
+    template <int D, bool COH>
+    __device__ static void load(const uint16_t* M, int64_t row, int gl, float (&x)[Lanes<true, D>::kEPL]) {
+        constexpr int L = Lanes<true, D>::kL;
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * D) + gl;
 #pragma unroll
-        for (int i = 0; i < kEPL / 2; ++i) {
+        for (int i = 0; i < Lanes<true, D>::kWPL; ++i) {
             uint32_t w;
             if constexpr (COH)
                 w = __hip_atomic_load(p + L * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,17 +131,26 @@ struct RowIO<true> {
             x[2 * i + 1] = bf16_hi(w);
         }
     }
-    // cur: the values this visit last saw (exact BF16), v: the FP32 results.
-    // Element h of the lane uses random half h of r.  out: the rounded values.
-    template <int L>
-    __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[kEPL],
-                                  const float (&v)[kEPL], uint4 r, float (&out)[kEPL]) {
-        uint32_t* p = reinterpret_cast<uint32_t*>(M + row * (L * kEPL)) + gl;
-        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+    // cur: the values this visit last saw (exact BF16), v: the FP32 results,
+    // r: the lane's Philox block (block gl mod d/8 of the row).  Word w of the
+    // row takes 32-bit output word w div (d/8) of its block (low half for the
+    // even element).  out: the rounded values.
+    template <int D>
+    __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[Lanes<true, D>::kEPL],
+                                  const float (&v)[Lanes<true, D>::kEPL], uint4 r,
+                                  float (&out)[Lanes<true, D>::kEPL]) {
+        using Ly = Lanes<true, D>;
+        constexpr int L = Ly::kL;
+        uint32_t* p = reinterpret_cast<uint32_t*>(M + row * D) + gl;
+        const int q0 = gl / Ly::kBlocks;
 #pragma unroll
-        for (int i = 0; i < kEPL / 2; ++i) {
-            const uint32_t t0 = bf16_sr(v[2 * i], rw[i] & 0xFFFFu);
-            const uint32_t t1 = bf16_sr(v[2 * i + 1], rw[i] >> 16);
+        for (int i = 0; i < Ly::kWPL; ++i) {
+            // output word q of the block, selected without indexing a
+            // register array by a lane-dependent value (that would go to scratch)
+            const int q = q0 + i * (L / Ly::kBlocks);
+            const uint32_t bits = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+            const uint32_t t0 = bf16_sr(v[2 * i], bits & 0xFFFFu);
+            const uint32_t t1 = bf16_sr(v[2 * i + 1], bits >> 16);
             out[2 * i] = __uint_as_float(t0 << 16);
             out[2 * i + 1] = __uint_as_float(t1 << 16);
             const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
@@ -138,42 +168,48 @@ __device__ __forceinline__ float sigmoidf_(float x) {
 }
 
 // UpdateEmbed (Algorithm 1) on samples u[0..k] of one source, u[0] the
-// positive: the source row is updated in registers along the chain and
-// written back once at the end.  Samples that are -1 or equal to the source
-// are skipped (a skipped negative is subtracted from `updates`, which the
-// callers precount).  BF16 rounding bits come from the stream (sid, epoch,
-// w2, kind sr_kind | slot t or 255 | block gl).  COH: loads bypass the
-// non-coherent caches (rows written by other waves of the same launch).
+// positive: the source row (row `src` of Ms) is updated in registers along
+// the chain and written back once at the end; the samples are rows of Mo.
+// Samples that are -1 or equal to `self` (the source's index in Mo, -1 if it
+// has none) are skipped; a skipped negative is subtracted from `updates`,
+// which the callers precount.  BF16 rounding bits come from the stream (sid,
+// epoch, w2, kind sr_kind | slot t or 255 | block blk_hi << 8 | gl mod d/8).
+// COH: loads bypass the non-coherent caches (rows written by other waves of
+// the same launch).
 template <bool BF16, int D, int KMAX, bool COH>
-__device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* M, int64_t src,
+__device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int64_t src,
+                                             typename RowIO<BF16>::Elem* Mo, int64_t self,
                                              const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
-                                             uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t key0,
-                                             uint32_t key1, unsigned long long* updates, int gl) {
-    constexpr int L = D / kEPL;
+                                             uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
+                                             uint32_t key0, uint32_t key1, unsigned long long* updates, int gl) {
+    using Ly = Lanes<BF16, D>;
+    constexpr int L = Ly::kL;
+    constexpr int E = Ly::kEPL;
     using IO = RowIO<BF16>;
-    float s[kEPL];
-    float m[KMAX + 1][kEPL];
-    IO::template load<L, COH>(M, src, gl, s);
+    const uint32_t blk = (blk_hi << 8) | static_cast<uint32_t>(gl % Ly::kBlocks);
+    float s[E];
+    float m[KMAX + 1][E];
+    IO::template load<D, COH>(Ms, src, gl, s);
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) {
-        if (u[t] >= 0 && u[t] != src) {
-            IO::template load<L, COH>(M, u[t], gl, m[t]);
+        if (t <= k && u[t] >= 0 && u[t] != self) {
+            IO::template load<D, COH>(Mo, u[t], gl, m[t]);
         } else {
 #pragma unroll
-            for (int e = 0; e < kEPL; ++e) m[t][e] = 0.0f;
+            for (int e = 0; e < E; ++e) m[t][e] = 0.0f;
         }
     }
 
     int done = 0;
-    float s0[kEPL];
+    float s0[E];
 #pragma unroll
-    for (int e = 0; e < kEPL; ++e) s0[e] = s[e];
+    for (int e = 0; e < E; ++e) s0[e] = s[e];
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) {
         if (t > k) break;
         const int32_t ut = u[t];
-        if (ut < 0 || ut == src) {
-            if (t > 0 && ut == src && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
+        if (ut < 0 || ut == self) {
+            if (t > 0 && ut >= 0 && ut == self && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
             continue;
         }
         // a row sampled earlier in this visit continues from its updated value
@@ -181,51 +217,47 @@ __device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* M, int6
         for (int tp = 0; tp < t; ++tp) {
             if (u[tp] == ut) {
 #pragma unroll
-                for (int e = 0; e < kEPL; ++e) m[t][e] = m[tp][e];
+                for (int e = 0; e < E; ++e) m[t][e] = m[tp][e];
             }
         }
         float x = 0.0f;
 #pragma unroll
-        for (int e = 0; e < kEPL; ++e) x = fmaf(s[e], m[t][e], x);
+        for (int e = 0; e < E; ++e) x = fmaf(s[e], m[t][e], x);
         x = group_sum<L>(x);
         const float b = (t == 0) ? 1.0f : 0.0f;
         const float g = (b - sigmoidf_(x)) * lr;
 #pragma unroll
-        for (int e = 0; e < kEPL; ++e) s[e] = fmaf(g, m[t][e], s[e]);
+        for (int e = 0; e < E; ++e) s[e] = fmaf(g, m[t][e], s[e]);
         if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(sid, epoch, w2,
-                                                   stream_word3(sr_kind, static_cast<uint32_t>(t),
-                                                                static_cast<uint32_t>(gl))),
-                                        key0, key1);
-            float v[kEPL], out[kEPL];
+            const uint4 bits = philox10(
+                make_uint4(sid, epoch, w2, stream_word3(sr_kind, static_cast<uint32_t>(t), blk)), key0, key1);
+            float v[E], out[E];
 #pragma unroll
-            for (int e = 0; e < kEPL; ++e) v[e] = fmaf(g, s[e], m[t][e]);
-            IO::template commit<L>(M, ut, gl, m[t], v, bits, out);
+            for (int e = 0; e < E; ++e) v[e] = fmaf(g, s[e], m[t][e]);
+            IO::template commit<D>(Mo, ut, gl, m[t], v, bits, out);
 #pragma unroll
-            for (int e = 0; e < kEPL; ++e) m[t][e] = out[e];
+            for (int e = 0; e < E; ++e) m[t][e] = out[e];
         } else {
-            float dx[kEPL];
+            float dx[E];
 #pragma unroll
-            for (int e = 0; e < kEPL; ++e) {
+            for (int e = 0; e < E; ++e) {
                 dx[e] = g * s[e];
                 m[t][e] += dx[e];
             }
-            IO::template add<L>(M, ut, gl, dx);
+            IO::template add<D>(Mo, ut, gl, dx);
         }
         ++done;
     }
     if (done) {
         if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(sid, epoch, w2,
-                                                   stream_word3(sr_kind, 0xFFu, static_cast<uint32_t>(gl))),
-                                        key0, key1);
-            float out[kEPL];
-            IO::template commit<L>(M, src, gl, s0, s, bits, out);
+            const uint4 bits = philox10(make_uint4(sid, epoch, w2, stream_word3(sr_kind, 0xFFu, blk)), key0, key1);
+            float out[E];
+            IO::template commit<D>(Ms, src, gl, s0, s, bits, out);
         } else {
-            float dx[kEPL];
+            float dx[E];
 #pragma unroll
-            for (int e = 0; e < kEPL; ++e) dx[e] = s[e] - s0[e];
-            IO::template add<L>(M, src, gl, dx);
+            for (int e = 0; e < E; ++e) dx[e] = s[e] - s0[e];
+            IO::template add<D>(Ms, src, gl, dx);
         }
     }
 }
@@ -285,8 +317,8 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
         }
     }
     if (!active) return;
-    update_chain<BF16, D, KMAX, MODE == kPersistent>(M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch,
-                                                     P.w2, 1u, P.key0, P.key1, P.updates, gl);
+    update_chain<BF16, D, KMAX, MODE == kPersistent>(M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src),
+                                                     P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates, gl);
 }
 
 }  // namespace train_detail

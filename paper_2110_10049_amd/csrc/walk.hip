@@ -35,6 +35,7 @@ using namespace train_detail;
 
 constexpr int kWalkThreads = 256;
 constexpr int kMaxWalkLen = 1024;
+constexpr int kLdsSteps = 16;     // walks of up to 15 steps are counted from LDS (16 KiB per block)
 
 struct WalkArgs {
     const void* offsets;
@@ -60,13 +61,19 @@ __global__ void k_pair_table(int32_t len, int32_t window, uint32_t* tab) {
 
 template <class Off>
 __global__ __launch_bounds__(kWalkThreads) void k_walks(WalkArgs A) {
+    __shared__ int32_t walk_lds[kLdsSteps * kWalkThreads];
     const int64_t v = static_cast<int64_t>(blockIdx.x) * kWalkThreads + threadIdx.x;
     unsigned long long cnt = 0;
     if (v < A.n) {
         const Off* off = static_cast<const Off*>(A.offsets);
         int32_t* w = A.walks + v * (A.len + 1);
+        // LDS copy of the walk for the update count: column per lane, so the
+        // lanes of a wave hit distinct banks
+        const bool lds_ok = A.updates && A.len < kLdsSteps;
+        int32_t* mine = walk_lds + threadIdx.x;
         int64_t cur = v;
         w[0] = static_cast<int32_t>(v);
+        if (lds_ok) mine[0] = static_cast<int32_t>(v);
         int32_t wl = 1;
         uint4 r = make_uint4(0, 0, 0, 0);
         for (int32_t i = 0; i < A.len; ++i) {
@@ -82,17 +89,23 @@ __global__ __launch_bounds__(kWalkThreads) void k_walks(WalkArgs A) {
             const int32_t nxt = A.indices[beg + scale_u32(word, deg)];
             if (nxt < 0 || nxt >= A.n) break;
             cur = nxt;
+            if (lds_ok) mine[wl * kWalkThreads] = nxt;
             w[wl++] = nxt;
         }
         for (int32_t i = wl; i <= A.len; ++i) w[i] = -1;
         if (A.updates) {
             // executed updates of this walk's pairs: the positives that differ
             // from their source plus k negatives per pair (a negative equal to
-            // the source is subtracted by the visit)
+            // the source is subtracted by the visit); the walk is read back
+            // from the lane's own LDS copy when it fits
             for (int32_t l = 0; l < A.P; ++l) {
                 const uint32_t ab = A.tab[l];
                 const int32_t a = static_cast<int32_t>(ab & 0xFFFFu), b = static_cast<int32_t>(ab >> 16);
-                if (b < wl) cnt += static_cast<unsigned long long>(A.k) + (w[a] != w[b] ? 1ull : 0ull);
+                if (b < wl) {
+                    const int32_t wa = lds_ok ? mine[a * kWalkThreads] : w[a];
+                    const int32_t wb = lds_ok ? mine[b * kWalkThreads] : w[b];
+                    cnt += static_cast<unsigned long long>(A.k) + (wa != wb ? 1ull : 0ull);
+                }
             }
         }
     }
@@ -152,14 +165,15 @@ __device__ __forceinline__ void walk_visit(const WalkTrain& T, int64_t r, int gl
 #pragma unroll
         for (int t = 1; t <= KMAX; ++t) u[t] = (t <= T.k) ? static_cast<int32_t>(scale_u32(wd[t], T.n)) : -1;
     }
-    update_chain<BF16, D, KMAX, false>(static_cast<Elem*>(T.emb), src, u, T.k, T.lr, static_cast<uint32_t>(r),
-                                       T.epoch, T.w2, 7u, T.key0, T.key1, T.updates, gl);
+    Elem* M = static_cast<Elem*>(T.emb);
+    update_chain<BF16, D, KMAX, false>(M, src, M, src, u, T.k, T.lr, static_cast<uint32_t>(r), T.epoch, T.w2, 7u, 0u,
+                                       T.key0, T.key1, T.updates, gl);
 }
 
 template <bool BF16, int D, int KMAX, bool SEQ>
 __global__ __launch_bounds__(kBlock) void k_walk_train(WalkTrain T) {
-    constexpr int L = D / kEPL;
-    constexpr int G = 64 / L;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     if constexpr (SEQ) {
@@ -179,7 +193,7 @@ using WalkLauncher = void (*)(const WalkTrain&, hipStream_t, bool);
 
 template <bool BF16, int D, int KMAX>
 void launch_walk(const WalkTrain& T, hipStream_t st, bool seq) {
-    constexpr int G = 64 / (D / kEPL);
+    constexpr int G = Lanes<BF16, D>::kG;
     if (seq) {
         hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, T);
     } else {

@@ -73,7 +73,8 @@ def test_pairs_bit_exact_full_scale20(gctx, orc):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("d,k,length,window,epochs", [(8, 1, 4, 2, 2), (16, 0, 6, 3, 2), (32, 3, 5, 2, 3),
-                                                      (64, 7, 3, 1, 2), (128, 15, 4, 4, 1), (256, 2, 2, 2, 2)])
+                                                      (64, 7, 3, 1, 2), (128, 15, 4, 4, 1), (256, 2, 2, 2, 2),
+                                                      (16, 1, 20, 2, 1)])
 def test_deterministic_matches_reference(gctx, orc, dtype, d, k, length, window, epochs):
     from paper_2110_10049_amd import gosh as G
     off, idx = _graph(8, 5)
