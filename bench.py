@@ -9,7 +9,10 @@ split), d = 128, k = 3 negatives, 600 epochs over all levels (p = 0.3),
 lr = 0.045, coarsening threshold 100.  The headline run stores rows in BF16
 (stochastic rounding, FP32 arithmetic); the same workload with FP32 rows is
 timed beside it, and both final embeddings are scored by link-prediction
-AUC on the held-out 20%.
+AUC on the held-out 20%.  Rows of negative samples are written with plain
+stores (the paper's lock-free writes) on levels of at least 65,536 vertices
+and with atomic adds elsewhere; positive and source rows always use atomic
+adds (--plain-neg-min 0: atomic adds everywhere).
 
 value = executed UpdateEmbed calls (edge-samples) per second of step wall
 time.  roofline: the dominant kernel is the level-0 training epoch; its
@@ -91,6 +94,9 @@ def parse():
     ap.add_argument("--overlap", type=int, default=1,
                     help="epochs per launch on levels of at least --overlap-min vertices (1: one epoch per launch)")
     ap.add_argument("--overlap-min", type=int, default=65536)
+    ap.add_argument("--plain-neg-min", type=int, default=65536,
+                    help="plain stores for negative rows on levels of at least this many vertices (0: atomic adds "
+                         "everywhere)")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -547,6 +553,7 @@ def walk_workload(a):
     n0, nnz = sp.n, len(sp.indices)
     log(f"graph ready: |V_train|={n0} nnz={nnz} ({time.time() - t0:.1f}s)")
     ctx = G.Context(0, seed=seeds["philox"])
+    ctx.set_plain_negatives(a.plain_neg_min)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
     cfg = EmbedConfig(d=d, epochs=E, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=threshold,
@@ -653,6 +660,7 @@ def main():
         del src_buf, dst_buf
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
+    ctx.set_plain_negatives(a.plain_neg_min)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
 
@@ -728,6 +736,7 @@ def main():
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
+                   "plain_negative_stores_min_vertices": a.plain_neg_min,
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),

@@ -100,6 +100,20 @@ gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on);
  * epochs_in_flight in [1, 64], min_vertices >= 0. */
 gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int64_t min_vertices);
 
+/* Write discipline of negative samples (Section 3.1 lets the sources of an
+ * epoch race on rows without locks).  By default every row change is applied
+ * with atomic adds, so no concurrent update is lost.  With min_vertices > 0,
+ * gosh_train and gosh_train_walks write the rows of negative samples with
+ * plain stores of the new value (the paper's lock-free discipline) on levels
+ * of at least min_vertices vertices: a negative is a uniform draw, so on a
+ * large level two visits rarely hold the same negative row at once, while
+ * the positive and source rows, which concentrate on high-degree vertices,
+ * keep their atomic adds.  A store may overwrite an update that another
+ * visit applied to the same row in the meantime (which the paper's kernel
+ * accepts for every row).  0 (the default) turns it off; ignored in
+ * deterministic mode.  min_vertices >= 0. */
+gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* Checks `g` against the graph convention (Section 4.1: the method works on

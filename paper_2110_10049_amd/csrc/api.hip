@@ -226,6 +226,12 @@ gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int6
     return GOSH_OK;
 }
 
+gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices) {
+    if (!ctx || min_vertices < 0) return GOSH_E_INVALID_ARG;
+    ctx->c.plain_neg_min = min_vertices;
+    return GOSH_OK;
+}
+
 gosh_status gosh_validate_csr(gosh_ctx* ctx, const gosh_csr* g, int check_symmetry) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     return guarded(ctx, [&] {

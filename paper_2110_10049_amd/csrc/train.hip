@@ -198,6 +198,7 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     P.span = 1;
     P.e_total = epochs;
     P.lr0 = lr;
+    P.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && L.n >= c->plain_neg_min) ? 1 : 0;
     for (int j = 0; j < epochs; j += span) {
         const double f = 1.0 - static_cast<double>(j) / static_cast<double>(epochs);
         P.lr = static_cast<float>(static_cast<double>(lr) * (f > 1e-4 ? f : 1e-4));

@@ -37,6 +37,7 @@ struct TrainParams {
     int32_t span;
     int32_t e_total;
     float lr0;
+    int32_t plain_neg;        // negatives written with plain stores instead of atomic adds
 };
 
 enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
@@ -97,6 +98,13 @@ struct RowIO<false> {
         }
     }
     template <int D>
+    __device__ static void store(float* M, int64_t row, int gl, const float (&x)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        float* p = M + row * D + gl;
+#pragma unroll
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i) p[L * i] = x[i];
+    }
+    template <int D>
     __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[Lanes<false, D>::kEPL]) {
         constexpr int L = Lanes<false, D>::kL;
         float* p = M + row * D + gl;
@@ -135,7 +143,8 @@ struct RowIO<true> {
     // r: the lane's Philox block (block gl mod d/8 of the row).  Word w of the
     // row takes 32-bit output word w div (d/8) of its block (low half for the
     // even element).  out: the rounded values.
-    template <int D>
+    // PLAIN: store the rounded words instead of adding the difference.
+    template <int D, bool PLAIN = false>
     __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[Lanes<true, D>::kEPL],
                                   const float (&v)[Lanes<true, D>::kEPL], uint4 r,
                                   float (&out)[Lanes<true, D>::kEPL]) {
@@ -153,12 +162,16 @@ struct RowIO<true> {
             const uint32_t t1 = bf16_sr(v[2 * i + 1], bits >> 16);
             out[2 * i] = __uint_as_float(t0 << 16);
             out[2 * i + 1] = __uint_as_float(t1 << 16);
-            const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
-                               (bf16_rne_bits(out[2 * i + 1] - cur[2 * i + 1]) << 16);
-            if (d != 0u)
-                __builtin_amdgcn_global_atomic_fadd_v2bf16(
-                    (__attribute__((address_space(1))) bf16x2_t*)(p + L * i),
-                    __builtin_bit_cast(bf16x2_t, d));
+            if constexpr (PLAIN) {
+                p[L * i] = (t0 & 0xFFFFu) | (t1 << 16);
+            } else {
+                const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
+                                   (bf16_rne_bits(out[2 * i + 1] - cur[2 * i + 1]) << 16);
+                if (d != 0u)
+                    __builtin_amdgcn_global_atomic_fadd_v2bf16(
+                        (__attribute__((address_space(1))) bf16x2_t*)(p + L * i),
+                        __builtin_bit_cast(bf16x2_t, d));
+            }
         }
     }
 };
@@ -181,7 +194,8 @@ __device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int
                                              typename RowIO<BF16>::Elem* Mo, int64_t self,
                                              const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
                                              uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
-                                             uint32_t key0, uint32_t key1, unsigned long long* updates, int gl) {
+                                             uint32_t key0, uint32_t key1, unsigned long long* updates, int gl,
+                                             bool plain_neg = false) {
     using Ly = Lanes<BF16, D>;
     constexpr int L = Ly::kL;
     constexpr int E = Ly::kEPL;
@@ -234,7 +248,8 @@ __device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int
             float v[E], out[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = fmaf(g, s[e], m[t][e]);
-            IO::template commit<D>(Mo, ut, gl, m[t], v, bits, out);
+            if (t > 0 && plain_neg) IO::template commit<D, true>(Mo, ut, gl, m[t], v, bits, out);
+            else IO::template commit<D>(Mo, ut, gl, m[t], v, bits, out);
 #pragma unroll
             for (int e = 0; e < E; ++e) m[t][e] = out[e];
         } else {
@@ -244,7 +259,8 @@ __device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int
                 dx[e] = g * s[e];
                 m[t][e] += dx[e];
             }
-            IO::template add<D>(Mo, ut, gl, dx);
+            if (t > 0 && plain_neg) IO::template store<D>(Mo, ut, gl, m[t]);
+            else IO::template add<D>(Mo, ut, gl, dx);
         }
         ++done;
     }
@@ -318,7 +334,8 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
     }
     if (!active) return;
     update_chain<BF16, D, KMAX, MODE == kPersistent>(M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src),
-                                                     P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates, gl);
+                                                     P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates, gl,
+                                                     MODE == kEpoch && P.plain_neg != 0);
 }
 
 }  // namespace train_detail

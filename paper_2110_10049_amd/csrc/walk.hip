@@ -135,6 +135,7 @@ struct WalkTrain {
     int k;
     uint32_t key0, key1, epoch, w2;
     unsigned long long* updates;
+    int32_t plain_neg;        // negatives written with plain stores
 };
 
 template <bool BF16, int D, int KMAX>
@@ -167,7 +168,7 @@ __device__ __forceinline__ void walk_visit(const WalkTrain& T, int64_t r, int gl
     }
     Elem* M = static_cast<Elem*>(T.emb);
     update_chain<BF16, D, KMAX, false>(M, src, M, src, u, T.k, T.lr, static_cast<uint32_t>(r), T.epoch, T.w2, 7u, 0u,
-                                       T.key0, T.key1, T.updates, gl);
+                                       T.key0, T.key1, T.updates, gl, T.plain_neg != 0);
 }
 
 template <bool BF16, int D, int KMAX, bool SEQ>
@@ -338,6 +339,7 @@ void train_walks(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     T.key1 = W.A.key1;
     T.w2 = W.A.w2;
     T.updates = W.A.updates;
+    T.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && L.n >= c->plain_neg_min) ? 1 : 0;
     // optional timing: events before the sampling, between sampling and
     // training, and after the training of every epoch
     std::vector<hipEvent_t> ev;

@@ -82,6 +82,7 @@ _SIGNATURES = [
     ("gosh_mem_in_use", C.c_int, [_P, C.POINTER(C.c_uint64)]),
     ("gosh_set_deterministic", C.c_int, [_P, C.c_int]),
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
+    ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
     ("gosh_validate_csr", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int]),
     ("gosh_coarsen", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int64, C.c_double, C.POINTER(_P)]),
     ("gosh_levels_single", C.c_int, [_P, C.POINTER(gosh_csr), C.POINTER(_P)]),
@@ -201,6 +202,10 @@ class Context:
     def set_epoch_overlap(self, epochs_in_flight: int, min_vertices: int = 0):
         """Concurrent epochs on levels of at least min_vertices vertices (1 = off)."""
         self.check(self._L.gosh_set_epoch_overlap(self.h, epochs_in_flight, min_vertices))
+
+    def set_plain_negatives(self, min_vertices: int):
+        """Plain stores for negative rows on levels of at least min_vertices vertices (0 = off)."""
+        self.check(self._L.gosh_set_plain_negatives(self.h, min_vertices))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -130,3 +130,50 @@ def test_overlap_with_zero_lr_is_identity(gctx):
     assert torch.equal(M, M0)
     with pytest.raises(G.GoshError):
         gctx.set_epoch_overlap(0, 0)
+
+
+def test_plain_negative_stores_keep_auc_on_large_levels(gctx, orc):
+    # negatives stored plainly (the paper's lock-free writes) on levels of at
+    # least 8192 vertices: same update count, AUC within 0.015 of the oracle
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import EmbedConfig, embed
+    sp = train_split(16, 16)
+    g = G.CSR.from_numpy(sp.offsets, sp.indices)
+    cfg = EmbedConfig(d=32, epochs=200, p=0.3, lr=0.045, k=3, threshold=100)
+    gctx.set_plain_negatives(8192)
+    try:
+        res = embed(gctx, g, cfg, lambda n, dd: torch.from_numpy(init_rows(n, dd, 3)).cuda())
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_negatives(0)
+    assert res.sizes[0] >= 8192
+    Mo, info = _oracle_embed(orc, sp, 32, 200, 0.3, 0.045, 3, 100, False)
+    assert int(res.updates.item()) == sum(info["updates"])
+    a_g = evaluate_auc(res.emb.cpu().numpy(), sp, seed=5)
+    a_o = evaluate_auc(Mo, sp, seed=5)
+    print(f"[e2e plain negatives] n0={res.sizes[0]} AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
+    assert abs(a_g - a_o) < 0.015
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_plain_negative_stores_zero_lr_is_identity(gctx, dtype):
+    from paper_2110_10049_amd import gosh as G
+    sp = train_split(12, 16)
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(sp.offsets, sp.indices))
+    M0 = torch.from_numpy(init_rows(sp.n, 64, 3)).cuda().to(dtype)
+    M = M0.clone()
+    c_plain = torch.zeros(1, dtype=torch.int64, device="cuda")
+    c_atomic = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gctx.set_plain_negatives(1)
+    try:
+        G.gosh_train(gctx, lv, 0, M, 5, 0.0, 3, 0, c_plain)
+        G.gosh_train_walks(gctx, lv, 0, M, 2, 0.0, 3, 4, 2)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_negatives(0)
+    G.gosh_train(gctx, lv, 0, M.clone(), 5, 0.0, 3, 0, c_atomic)
+    torch.cuda.synchronize()
+    assert torch.equal(M, M0)
+    assert int(c_plain.item()) == int(c_atomic.item())
+    with pytest.raises(G.GoshError):
+        gctx.set_plain_negatives(-1)
