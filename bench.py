@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--overlap", type=int, default=1,
                     help="epochs per launch on levels of at least --overlap-min vertices (1: one epoch per launch)")
     ap.add_argument("--overlap-min", type=int, default=65536)
+    ap.add_argument("--coarsen", default="exact", choices=["exact", "lock-skip"],
+                    help="mapping step of the coarsening (lock-skip: the paper's parallel scheme)")
     ap.add_argument("--plain-neg-min", type=int, default=65536,
                     help="plain stores for negative rows on levels of at least this many vertices (0: atomic adds "
                          "everywhere)")
@@ -661,6 +663,7 @@ def main():
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     ctx.set_plain_negatives(a.plain_neg_min)
+    ctx.set_coarsen_mode(G.GOSH_COARSEN_LOCK_SKIP if a.coarsen == "lock-skip" else G.GOSH_COARSEN_EXACT)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
 
@@ -670,14 +673,18 @@ def main():
                           batch_mode={"auto": G.GOSH_BATCH_AUTO, "persistent": G.GOSH_BATCH_PERSISTENT,
                                       "graph": G.GOSH_BATCH_EPOCH_GRAPH}[a.batch_mode])
         lv = G.gosh_coarsen(ctx, g, threshold)
-        n_c = lv.sizes()[-1]
+        # the lock-and-skip mapping's coarsest size varies from run to run:
+        # keep the first rows of a larger draw resident (init_rows(n) is a
+        # prefix of init_rows(N) for n <= N)
+        n_c = lv.sizes()[-1] * (4 if a.coarsen == "lock-skip" else 1)
         f = init_rows(n_c, d, seeds["init"])
         init_dev = torch.from_numpy(f).cuda().to(dtype)   # RNE to BF16, resident before timing
         del lv
 
         def init_fn(n, dd):
-            assert n == n_c
-            return init_dev.clone()
+            if n > n_c:
+                raise RuntimeError(f"coarsest level has {n} vertices, more than the {n_c} prepared rows")
+            return init_dev[:n].clone()
 
         for _ in range(warmup):
             embed(ctx, g, cfg, init_fn)
@@ -736,7 +743,7 @@ def main():
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
-                   "plain_negative_stores_min_vertices": a.plain_neg_min,
+                   "plain_negative_stores_min_vertices": a.plain_neg_min, "coarsening": a.coarsen,
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),

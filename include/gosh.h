@@ -90,6 +90,26 @@ gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes);
  * sources of an epoch run concurrently without locks (Section 3.1). */
 gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on);
 
+/* Mapping step of MultiEdgeCollapse used by gosh_coarsen. */
+typedef enum {
+    GOSH_COARSEN_EXACT = 0,      /* Algorithm 4's result exactly (default)                    */
+    GOSH_COARSEN_LOCK_SKIP = 1   /* the paper's parallel lock-and-skip mapping (Section 4)    */
+} gosh_coarsen_mode;
+
+/* Selects the mapping step of gosh_coarsen.  GOSH_COARSEN_EXACT computes the
+ * clusters of sequential Algorithm 4 (bit-exact, deterministic).
+ * GOSH_COARSEN_LOCK_SKIP runs the parallel scheme of Section 4: vertices are
+ * taken in Algorithm 4's order by concurrent threads, `batch` of them per
+ * launch (0: max(64, n/64) per level); an unmarked vertex is claimed as a
+ * hub and marks its unmarked neighbours over eligible edges, each mark a
+ * compare-and-swap, and a vertex already marked by another thread is
+ * skipped.  Every cluster is still a hub with eligible neighbours, cluster
+ * ids count hubs in Algorithm 4's order, but the clusters depend on thread
+ * timing (more, smaller clusters than the exact mapping when many vertices
+ * run at once).  In deterministic mode one wave takes all vertices in
+ * order, which is Algorithm 4 exactly.  batch >= 0. */
+gosh_status gosh_set_coarsen_mode(gosh_ctx* ctx, gosh_coarsen_mode mode, int64_t batch);
+
 /* Concurrent epochs on large levels (the extension the paper suggests in
  * Section 6.3: overlapping epochs on the upper levels, full synchronisation
  * elsewhere): gosh_train runs `epochs_in_flight` consecutive epochs in one

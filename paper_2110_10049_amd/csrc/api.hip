@@ -226,6 +226,14 @@ gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int6
     return GOSH_OK;
 }
 
+gosh_status gosh_set_coarsen_mode(gosh_ctx* ctx, gosh_coarsen_mode mode, int64_t batch) {
+    if (!ctx || batch < 0 || (mode != GOSH_COARSEN_EXACT && mode != GOSH_COARSEN_LOCK_SKIP))
+        return GOSH_E_INVALID_ARG;
+    ctx->c.coarsen_mode = mode;
+    ctx->c.claim_batch = batch;
+    return GOSH_OK;
+}
+
 gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices) {
     if (!ctx || min_vertices < 0) return GOSH_E_INVALID_ARG;
     ctx->c.plain_neg_min = min_vertices;

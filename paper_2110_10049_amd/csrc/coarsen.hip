@@ -231,6 +231,58 @@ __global__ void k_assign_wave(int64_t n, const int64_t* lstart, const int32_t* l
     }
 }
 
+// ---------------------------------------------------------------- lock-and-skip mapping
+// The paper's parallel coarsening (Section 4, parallelisation): vertices are
+// taken in pi order by concurrent threads; a thread that finds its vertex v
+// unmarked claims it as a hub (owner[v] = v) and then marks every unmarked
+// neighbour u over an eligible edge (owner[u] = v).  Each claim is one
+// compare-and-swap from -1, so a mark is never overwritten, and a vertex
+// that another thread marked first is skipped (the paper's lock that fails).
+// Vertices of ranks [r0, r1) run concurrently; ranks in later launches see
+// all earlier claims.  One wave over all ranks is Algorithm 4 exactly.
+// One wave per vertex (a thread per vertex would leave a hub's whole
+// neighbour list to one lane): lane 0 claims, the wave marks the neighbours.
+// With one wave in the grid the ranks run strictly in order.
+template <class Off>
+__global__ void k_claim(const Off* off, const int32_t* idx, const uint32_t* perm, int64_t r0, int64_t r1,
+                             const uint8_t* light, int32_t* owner) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); i < r1 - r0;
+         i += static_cast<int64_t>(gridDim.x) * wpb) {
+        const int64_t v = perm[r0 + i];
+        int won = 0;
+        if (lane == 0 && __hip_atomic_load(owner + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1)
+            won = atomicCAS(owner + v, -1, static_cast<int32_t>(v)) == -1 ? 1 : 0;
+        if (__shfl(won, 0, 64) == 0) continue;
+        const bool lv = light[v] != 0;
+        for (int64_t e = off[v] + lane, end = off[v + 1]; e < end; e += 64) {
+            const int32_t u = idx[e];
+            if (!(lv || light[u])) continue;
+            if (__hip_atomic_load(owner + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1)
+                atomicCAS(owner + u, -1, static_cast<int32_t>(v));
+        }
+    }
+}
+
+__global__ void k_owner_hub_flags(const uint32_t* perm, int64_t n, const int32_t* owner, int32_t* hf) {
+    GRID_STRIDE(r, n) hf[r] = owner[perm[r]] == static_cast<int32_t>(perm[r]) ? 1 : 0;
+}
+
+// Cluster id of v = number of hubs before its hub in pi order.
+__global__ void k_owner_assign(int64_t n, const int32_t* owner, const int32_t* rank, const int64_t* cid_by_rank,
+                               int32_t* map, unsigned int* bad) {
+    GRID_STRIDE(v, n) {
+        const int32_t h = owner[v];
+        if (h < 0 || h >= n) {   // cannot happen once every rank was processed
+            map[v] = 0;
+            atomicOr(bad, 1u);
+            continue;
+        }
+        map[v] = static_cast<int32_t>(cid_by_rank[rank[h]]);
+    }
+}
+
 __global__ void k_cluster_sizes(const int32_t* map, int64_t n, int32_t* clsz) {
     GRID_STRIDE(v, n) atomicAdd(&clsz[map[v]], 1);
 }
@@ -457,6 +509,104 @@ DevBuf<int32_t> validate_structure(Ctx* c, const Off* off, const int32_t* idx, i
     return src;
 }
 
+// Exact mapping: each vertex's eligible earlier neighbours, synchronous hub
+// selection rounds, then the assignment.  Returns the cluster count.
+template <class Off>
+int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const int32_t* src, const uint32_t* perm,
+                  const int32_t* rank_p, const uint8_t* light_p, bool dense, unsigned int* bad) {
+    const int64_t n = L.n, nnz = L.nnz;
+    DevBuf<int32_t> lower(c, std::max<int64_t>(nnz, 1));
+    DevBuf<int64_t> lstart(c, n + 1);
+    {
+        DevBuf<int32_t> flag(c, std::max<int64_t>(nnz, 1));
+        DevBuf<int64_t> pos(c, std::max<int64_t>(nnz, 1));
+        if (nnz > 0) {
+            hipLaunchKernelGGL(k_flag_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz,
+                               light_p, rank_p, flag.p);
+            GOSH_HIP(hipGetLastError());
+            scan_i32_to_i64(c, flag.p, pos.p, nnz, nullptr);
+            hipLaunchKernelGGL(k_write_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, flag.p,
+                               pos.p, lower.p);
+            GOSH_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL((k_lower_starts<Off>), grid_for(n + 1), dim3(kThreads), 0, c->stream, off, n, nnz,
+                           flag.p, pos.p, lstart.p);
+        GOSH_HIP(hipGetLastError());
+    }
+
+    // hub selection rounds; each round decides at least the earliest
+    // undecided vertex, so the loop ends; dense levels (average degree >= 64)
+    // scan each segment with a whole wave
+    DevBuf<uint8_t> state(c, n);
+    fill(c, state.p, n, 0);
+    for (int64_t round = 0;; ++round) {
+        GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
+        GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
+        if (dense)
+            hipLaunchKernelGGL(k_round_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
+                               lower.p, state.p, scratch_u64(c, 1));
+        else
+            hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                               scratch_u64(c, 1));
+        GOSH_HIP(hipGetLastError());
+        if (read_u64(c, scratch_u64(c, 1)) == 0) break;
+    }
+
+    // cluster ids: hubs counted in pi order
+    DevBuf<int32_t> hf(c, n);
+    DevBuf<int64_t> cid(c, n);
+    hipLaunchKernelGGL(k_hub_flags_by_rank, grid_for(n), dim3(kThreads), 0, c->stream, perm, n, state.p,
+                       hf.p);
+    GOSH_HIP(hipGetLastError());
+    int64_t n_next = 0;
+    scan_i32_to_i64(c, hf.p, cid.p, n, &n_next);
+    hf.reset();
+    L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
+    if (dense)
+        hipLaunchKernelGGL(k_assign_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
+                           lower.p, state.p, rank_p, cid.p, L.map, bad);
+    else
+        hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+                           rank_p, cid.p, L.map, bad);
+    GOSH_HIP(hipGetLastError());
+    return n_next;
+}
+
+// Lock-and-skip mapping (k_claim), in launches of c->claim_batch ranks (one
+// wave over all ranks in deterministic mode).  Returns the cluster count.
+template <class Off>
+int64_t map_lock_skip(Ctx* c, Level& L, const Off* off, const int32_t* idx, const uint32_t* perm,
+                      const int32_t* rank_p, const uint8_t* light_p, unsigned int* bad) {
+    const int64_t n = L.n;
+    DevBuf<int32_t> owner(c, n);
+    fill(c, owner.p, n, 0xFF);
+    if (c->deterministic) {
+        hipLaunchKernelGGL((k_claim<Off>), dim3(1), dim3(64), 0, c->stream, off, idx, perm, int64_t{0}, n, light_p,
+                           owner.p);
+        GOSH_HIP(hipGetLastError());
+    } else {
+        const int64_t batch = c->claim_batch > 0 ? c->claim_batch : std::max<int64_t>(64, ceil_div(n, 64));
+        for (int64_t r0 = 0; r0 < n; r0 += batch) {
+            const int64_t r1 = std::min(n, r0 + batch);
+            hipLaunchKernelGGL((k_claim<Off>), grid_for(r1 - r0, kThreads / 64), dim3(kThreads), 0, c->stream, off,
+                               idx, perm, r0, r1, light_p, owner.p);
+            GOSH_HIP(hipGetLastError());
+        }
+    }
+    DevBuf<int32_t> hf(c, n);
+    DevBuf<int64_t> cid(c, n);
+    hipLaunchKernelGGL(k_owner_hub_flags, grid_for(n), dim3(kThreads), 0, c->stream, perm, n, owner.p, hf.p);
+    GOSH_HIP(hipGetLastError());
+    int64_t n_next = 0;
+    scan_i32_to_i64(c, hf.p, cid.p, n, &n_next);
+    hf.reset();
+    L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
+    hipLaunchKernelGGL(k_owner_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, owner.p, rank_p, cid.p, L.map,
+                       bad);
+    GOSH_HIP(hipGetLastError());
+    return n_next;
+}
+
 template <class Off>
 void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     const int64_t n = L.n, nnz = L.nnz;
@@ -486,74 +636,21 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     hipLaunchKernelGGL(k_rank_from_perm, grid_for(n), dim3(kThreads), 0, c->stream, perm.p, n, rank.p);
     GOSH_HIP(hipGetLastError());
 
-    // row of every entry, and each vertex's eligible earlier neighbours
+    // row of every entry (for the coarse graph)
     DevBuf<int32_t> src_own;
     if (!src_in) src_own = expand_rows(c, off, n, nnz);
     const int32_t* src = src_in ? src_in->p : src_own.p;
-    DevBuf<int32_t> lower(c, std::max<int64_t>(nnz, 1));
-    DevBuf<int64_t> lstart(c, n + 1);
-    {
-        DevBuf<int32_t> flag(c, std::max<int64_t>(nnz, 1));
-        DevBuf<int64_t> pos(c, std::max<int64_t>(nnz, 1));
-        if (nnz > 0) {
-            hipLaunchKernelGGL(k_flag_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz,
-                               light.p, rank.p, flag.p);
-            GOSH_HIP(hipGetLastError());
-            scan_i32_to_i64(c, flag.p, pos.p, nnz, nullptr);
-            hipLaunchKernelGGL(k_write_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, flag.p,
-                               pos.p, lower.p);
-            GOSH_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL((k_lower_starts<Off>), grid_for(n + 1), dim3(kThreads), 0, c->stream, off, n, nnz,
-                           flag.p, pos.p, lstart.p);
-        GOSH_HIP(hipGetLastError());
-    }
-    light.reset();
-
-    // hub selection rounds; each round decides at least the earliest
-    // undecided vertex, so the loop ends
-    // dense levels (average degree >= 64) scan each segment with a whole wave
     const bool dense = nnz >= 64 * n;
-    DevBuf<uint8_t> state(c, n);
-    fill(c, state.p, n, 0);
-    for (int64_t round = 0;; ++round) {
-        GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
-        GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
-        if (dense)
-            hipLaunchKernelGGL(k_round_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
-                               lower.p, state.p, scratch_u64(c, 1));
-        else
-            hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                               scratch_u64(c, 1));
-        GOSH_HIP(hipGetLastError());
-        if (read_u64(c, scratch_u64(c, 1)) == 0) break;
-    }
-
-    // cluster ids: hubs counted in pi order
-    DevBuf<int32_t> hf(c, n);
-    DevBuf<int64_t> cid(c, n);
-    hipLaunchKernelGGL(k_hub_flags_by_rank, grid_for(n), dim3(kThreads), 0, c->stream, perm.p, n, state.p,
-                       hf.p);
-    GOSH_HIP(hipGetLastError());
-    int64_t n_next = 0;
-    scan_i32_to_i64(c, hf.p, cid.p, n, &n_next);
-    hf.reset();
-    L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
     unsigned int* bad = reinterpret_cast<unsigned int*>(scratch_u64(c, 4));
     GOSH_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
-    if (dense)
-        hipLaunchKernelGGL(k_assign_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
-                           lower.p, state.p, rank.p, cid.p, L.map, bad);
+    int64_t n_next = 0;
+    if (c->coarsen_mode == GOSH_COARSEN_LOCK_SKIP)
+        n_next = map_lock_skip(c, L, off, idx, perm.p, rank.p, light.p, bad);
     else
-        hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                           rank.p, cid.p, L.map, bad);
-    GOSH_HIP(hipGetLastError());
-    cid.reset();
-    state.reset();
+        n_next = map_exact(c, L, off, idx, src, perm.p, rank.p, light.p, dense, bad);
+    light.reset();
     rank.reset();
     perm.reset();
-    lower.reset();
-    lstart.reset();
 
     // coarse graph: distinct pairs (map v, map u), map v != map u, rows ascending
     void* noff = nullptr;
