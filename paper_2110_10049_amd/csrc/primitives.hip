@@ -166,7 +166,7 @@ void scan_impl(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int
 
 // ---------------------------------------------------------------- radix sort
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 32;
+constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kWaves = kSortThreads / 64;
@@ -187,31 +187,72 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, int6
     hist[static_cast<int64_t>(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Scatters one tile: keys of equal digit keep their input order (stable).
-// The tile is consumed in rounds of 256 consecutive keys; inside a round a
-// key's rank among equal digits is (earlier waves' counts) + (earlier lanes
-// of its own wave with the same digit, found with 8 ballots).
+// Scatters one tile, stable (keys of equal digit keep their input order).
+// All keys of the tile are loaded first; the tile is then ranked in rounds of
+// 256 consecutive keys (a key's rank among equal digits: earlier rounds,
+// earlier waves of its round, earlier lanes of its wave found with 8 ballots)
+// and placed at its tile-local position in LDS, so that the final copy to
+// the output writes each digit's run of the tile with consecutive lanes.
 template <class K, bool VALS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K* keys_out,
                                                                 const uint32_t* vals,
                                                                 uint32_t* vals_out, int64_t n,
                                                                 int shift, const int64_t* offs,
                                                                 int64_t nb) {
-    __shared__ int64_t base_off[kRadix];
+    __shared__ int64_t base_off[kRadix];     // output position of the tile's first key of each digit
+    __shared__ int local_start[kRadix];      // tile position of the first key of each digit
+    __shared__ int placed[kRadix];           // keys of each digit placed by earlier rounds
     __shared__ int wave_cnt[kWaves][kRadix];
+    __shared__ int wave_tot[kWaves];
+    __shared__ K sk[kSortTile];
+    __shared__ uint32_t sv[VALS ? kSortTile : 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tile = static_cast<int64_t>(blockIdx.x) * kSortTile;
+    const int len = static_cast<int>(n - tile < kSortTile ? n - tile : kSortTile);
+
+    K key[kSortItems];
+    uint32_t val[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = r * kSortThreads + tid;
+        key[r] = i < len ? keys[tile + i] : K(0);
+        val[r] = (VALS && i < len) ? vals[tile + i] : 0u;
+    }
     base_off[tid] = offs[static_cast<int64_t>(tid) * nb + blockIdx.x];
+    local_start[tid] = 0;
+    placed[tid] = 0;
 #pragma unroll
     for (int i = 0; i < kWaves; ++i) wave_cnt[i][tid] = 0;
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (r * kSortThreads + tid < len) atomicAdd(&local_start[static_cast<int>((key[r] >> shift) & (kRadix - 1))], 1);
+    __syncthreads();
+    {
+        // exclusive scan of the 256 digit counts, one per thread
+        const int cnt = local_start[tid];
+        int inc = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) wave_tot[w] = inc;
+        __syncthreads();
+        int before = 0;
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i)
+            if (i < w) before += wave_tot[i];
+        local_start[tid] = before + inc - cnt;
+    }
+    __syncthreads();
+
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * kSortTile;
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = tile + static_cast<int64_t>(r) * kSortThreads + tid;
-        const bool valid = idx < n;
-        K key = valid ? keys[idx] : K(0);
-        uint32_t val = (VALS && valid) ? vals[idx] : 0u;
-        const int digit = static_cast<int>((key >> shift) & (kRadix - 1));
+        if (r * kSortThreads >= len) break;   // the same for the whole block
+        const bool valid = r * kSortThreads + tid < len;
+        const int digit = static_cast<int>((key[r] >> shift) & (kRadix - 1));
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -220,14 +261,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K
             peers &= bit ? m : ~m;
         }
         const int rank = __popcll(peers & lt_mask);
-        const bool leader = valid && rank == 0;
-        if (leader) wave_cnt[w][digit] = __popcll(peers);
+        if (valid && rank == 0) wave_cnt[w][digit] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            int64_t pos = base_off[digit] + rank;
+            int pos = local_start[digit] + placed[digit] + rank;
             for (int i = 0; i < w; ++i) pos += wave_cnt[i][digit];
-            keys_out[pos] = key;
-            if constexpr (VALS) vals_out[pos] = val;
+            sk[pos] = key[r];
+            if constexpr (VALS) sv[pos] = val[r];
         }
         __syncthreads();
         {
@@ -237,12 +277,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K
                 add += wave_cnt[i][tid];
                 wave_cnt[i][tid] = 0;
             }
-            base_off[tid] += add;
+            placed[tid] += add;
         }
         __syncthreads();
-        if (tile + static_cast<int64_t>(r + 1) * kSortThreads >= n) break;
+    }
+    for (int i = tid; i < len; i += kSortThreads) {
+        const K k = sk[i];
+        const int digit = static_cast<int>((k >> shift) & (kRadix - 1));
+        const int64_t pos = base_off[digit] + (i - local_start[digit]);
+        keys_out[pos] = k;
+        if constexpr (VALS) vals_out[pos] = sv[i];
     }
 }
+
 
 template <class K, bool VALS>
 void radix_sort_impl(Ctx* c, K* keys, K* keys_tmp, uint32_t* vals, uint32_t* vals_tmp, int64_t n,
