@@ -84,6 +84,13 @@ gosh_status gosh_sync(gosh_ctx* ctx);
 const char* gosh_last_error(const gosh_ctx* ctx);
 /* Bytes currently allocated by the library for this context. */
 gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes);
+/* Releases the device blocks the context keeps cached for reuse (every
+ * temporary of the library returns to this cache, and later calls take
+ * blocks of a fitting size from it before allocating).  Waits for the
+ * context stream.  Live levels, networks and the caller's buffers are not
+ * affected. */
+gosh_status gosh_trim(gosh_ctx* ctx);
+
 /* Debug mode: when on, gosh_train visits sources strictly one after another
  * in ascending id order (the sequential semantics of Algorithm 3 with its
  * parallel loop run in order), so results are reproducible.  Default off:

@@ -213,6 +213,14 @@ gosh_status gosh_mem_in_use(const gosh_ctx* ctx, uint64_t* bytes) {
     return GOSH_OK;
 }
 
+gosh_status gosh_trim(gosh_ctx* ctx) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        set_device(&ctx->c);
+        ctx->c.trim();
+    });
+}
+
 gosh_status gosh_set_deterministic(gosh_ctx* ctx, int on) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     ctx->c.deterministic = on != 0;

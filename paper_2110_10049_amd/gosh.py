@@ -84,6 +84,7 @@ _SIGNATURES = [
     ("gosh_set_deterministic", C.c_int, [_P, C.c_int]),
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
+    ("gosh_trim", C.c_int, [_P]),
     ("gosh_set_coarsen_mode", C.c_int, [_P, C.c_int, C.c_int64]),
     ("gosh_validate_csr", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int]),
     ("gosh_coarsen", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int64, C.c_double, C.POINTER(_P)]),
@@ -204,6 +205,10 @@ class Context:
     def set_epoch_overlap(self, epochs_in_flight: int, min_vertices: int = 0):
         """Concurrent epochs on levels of at least min_vertices vertices (1 = off)."""
         self.check(self._L.gosh_set_epoch_overlap(self.h, epochs_in_flight, min_vertices))
+
+    def trim(self):
+        """Release the device blocks cached by the context."""
+        self.check(self._L.gosh_trim(self.h))
 
     def set_coarsen_mode(self, mode: int, batch: int = 0):
         """GOSH_COARSEN_EXACT (default) or GOSH_COARSEN_LOCK_SKIP with `batch` vertices per launch."""
