@@ -280,7 +280,7 @@ typedef enum {
  * not wait for one another).  d, k and dtype are shared.  Meant for many
  * small graphs and for small coarse levels, where one launch per epoch and
  * graph would leave the device mostly idle.  GOSH_BATCH_AUTO times the
- * executions on a two-epoch dry run over scratch copies of the rows the
+ * executions on a dry run of up to 8 epochs over scratch copies of the rows the
  * first time a (dtype, d, k, size class) is seen and caches the winner (also
  * appended to the file named by the GOSH_TUNE_CACHE environment variable).
  * chosen_out (may be NULL) receives {mode, blocks per CU, chunk length} of

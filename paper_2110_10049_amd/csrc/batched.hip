@@ -17,7 +17,7 @@
 //    that still train in that round, the rounds recorded as a chain of
 //    kernel nodes of one hipGraph and launched together.
 // The autotuner times both (persistent with several grid sizes and chunk
-// lengths) on a two-epoch dry run over scratch copies of the embeddings and
+// lengths) on a dry run of up to 8 epochs over scratch copies of the embeddings and
 // caches the winner per (dtype, d, k, size class).
 #include <hip/hip_runtime.h>
 
@@ -346,8 +346,10 @@ void run(Ctx* c, Plan& P, const RunShape& R, const Kernels& K, int d, int k, int
         A.spin_limit = 1ull << 22;   // a few seconds of polling
         int cus = 0;
         GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-        const int64_t tasks = round_start[max_e];
-        const int64_t waves = std::min<int64_t>(static_cast<int64_t>(cus) * R.blocks_per_cu * (kBlock / 64), tasks);
+        // no more waves than tasks in the first (largest) epoch round: extra
+        // waves could only poll the done counters of epochs not yet reached
+        const int64_t round0 = round_start[1] - round_start[0];
+        const int64_t waves = std::min<int64_t>(static_cast<int64_t>(cus) * R.blocks_per_cu * (kBlock / 64), round0);
         const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, ceil_div(waves, kBlock / 64)));
         void* args[] = {&A};
         GOSH_HIP(hipLaunchKernel(K.persist, dim3(blocks), dim3(kBlock), args, 0, c->stream));
@@ -414,7 +416,10 @@ std::string tune_key(gosh_dtype dt, int d, int k, const Plan& P) {
 }
 
 RunShape autotune(Ctx* c, Plan& P, const Kernels& K, gosh_dtype dt, int d, int k) {
-    // candidates timed on a two-epoch dry run over scratch copies of the rows
+    // candidates timed on a dry run of up to 8 epochs over scratch copies of
+    // the rows (two epochs hide the cost of waiting on earlier epochs, which
+    // dominates a job with many short epochs)
+    const int dry = std::max(1, std::min(P.max_e, 8));
     const size_t elem = dt == GOSH_BF16 ? 2 : 4;
     size_t bytes = 0;
     for (const auto& J : P.jobs) bytes += static_cast<size_t>(J.n) * d * elem;
@@ -446,7 +451,7 @@ RunShape autotune(Ctx* c, Plan& P, const Kernels& K, gosh_dtype dt, int d, int k
         run(c, T, cand[1], K, d, k, 1, nullptr);   // warm-up
         for (const auto& R : cand) {
             GOSH_HIP(hipEventRecord(a, c->stream));
-            run(c, T, R, K, d, k, 2, nullptr);
+            run(c, T, R, K, d, k, dry, nullptr);
             GOSH_HIP(hipEventRecord(b, c->stream));
             GOSH_HIP(hipEventSynchronize(b));
             float ms = 0;

@@ -145,3 +145,25 @@ def test_config2_full_size(gctx, orc):
     sizes = lv.sizes()
     print("[coarsen parity] level sizes", sizes, flush=True)
     assert sizes[0] == sp.n and len(sizes) >= 4
+
+
+def test_trim_releases_cached_blocks(gctx, orc):
+    # temporaries return to the context cache; gosh_trim frees them and later
+    # calls allocate again with the same results
+    from paper_2110_10049_amd import gosh as G
+    off, idx = rmat_csr(11, 8, 5)
+    ctx = G.Context(0, seed=4)
+    try:
+        g = G.CSR.from_numpy(off, idx)
+        lv = G.gosh_coarsen(ctx, g, 8)
+        first = [lv.copy_out(i) for i in range(lv.count() - 1)]
+        held = ctx.mem_in_use()
+        del lv
+        ctx.trim()
+        assert ctx.mem_in_use() < held
+        lv = G.gosh_coarsen(ctx, g, 8)
+        for i, (o, x, m) in enumerate(first):
+            o2, x2, m2 = lv.copy_out(i)
+            assert np.array_equal(o, o2) and np.array_equal(x, x2) and np.array_equal(m, m2)
+    finally:
+        ctx.close()
