@@ -288,26 +288,21 @@ __global__ void k_cluster_sizes(const int32_t* map, int64_t n, int32_t* clsz) {
 }
 
 // ---------------------------------------------------------------- coarse graph
-__global__ void k_flag_cross(const int32_t* src, const int32_t* idx, int64_t nnz, const int32_t* map,
-                             int32_t* flag) {
-    GRID_STRIDE(p, nnz) flag[p] = map[src[p]] != map[idx[p]] ? 1 : 0;
-}
-
+// Key of every entry: (map v) << bb | (map u) for an entry between two
+// clusters, `sent` (above every such key in the low 2 bb bits) inside one.
 template <class K>
-__global__ void k_write_pairs(const int32_t* src, const int32_t* idx, int64_t nnz, const int32_t* map,
-                              const int32_t* flag, const int64_t* pos, int bb, K* keys) {
+__global__ void k_write_pairs(const int32_t* src, const int32_t* idx, int64_t nnz, const int32_t* map, int bb,
+                              K sent, K* keys) {
     GRID_STRIDE(p, nnz) {
-        if (flag[p]) {
-            const K a = static_cast<K>(static_cast<uint32_t>(map[src[p]]));
-            const K b = static_cast<K>(static_cast<uint32_t>(map[idx[p]]));
-            keys[pos[p]] = (a << bb) | b;
-        }
+        const uint32_t a = static_cast<uint32_t>(map[src[p]]);
+        const uint32_t b = static_cast<uint32_t>(map[idx[p]]);
+        keys[p] = a != b ? (static_cast<K>(a) << bb) | static_cast<K>(b) : sent;
     }
 }
 
 template <class K>
-__global__ void k_flag_unique(const K* keys, int64_t m, int32_t* flag) {
-    GRID_STRIDE(i, m) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+__global__ void k_flag_unique(const K* keys, int64_t m, K sent, int32_t* flag) {
+    GRID_STRIDE(i, m) flag[i] = (keys[i] != sent && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
 }
 
 template <class K>
@@ -415,20 +410,17 @@ template <class K>
 int64_t build_coarse(Ctx* c, const int32_t* src, const int32_t* idx, int64_t nnz, const int32_t* map,
                      int64_t n_next, bool off64, void** off_out, int32_t** idx_out) {
     const int bb = std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(n_next - 1, 0))));
-    DevBuf<int32_t> flag(c, std::max<int64_t>(nnz, 1));
-    DevBuf<int64_t> pos(c, std::max<int64_t>(nnz, 1));
-    int64_t m = 0;
-    if (nnz > 0) {
-        hipLaunchKernelGGL(k_flag_cross, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz,
-                           map, flag.p);
-        GOSH_HIP(hipGetLastError());
-        scan_i32_to_i64(c, flag.p, pos.p, nnz, &m);
-    }
+    // every entry gets a key; entries inside a cluster get the sentinel, which
+    // the sort moves behind all others and the unique pass drops
+    const K sent = 2 * bb >= static_cast<int>(8 * sizeof(K)) ? ~K(0) : (K(1) << (2 * bb)) - K(1);
+    const int64_t m = nnz;
     DevBuf<K> keys(c, std::max<int64_t>(m, 1)), tmp(c, std::max<int64_t>(m, 1));
+    DevBuf<int32_t> flag(c, std::max<int64_t>(m, 1));
+    DevBuf<int64_t> pos(c, std::max<int64_t>(m, 1));
     int64_t nnz_next = 0;
     if (m > 0) {
-        hipLaunchKernelGGL((k_write_pairs<K>), grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx,
-                           nnz, map, flag.p, pos.p, bb, keys.p);
+        hipLaunchKernelGGL((k_write_pairs<K>), grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz, map, bb,
+                           sent, keys.p);
         GOSH_HIP(hipGetLastError());
         if constexpr (sizeof(K) == 4)
             radix_sort_u32(c, reinterpret_cast<uint32_t*>(keys.p), reinterpret_cast<uint32_t*>(tmp.p),
@@ -436,7 +428,7 @@ int64_t build_coarse(Ctx* c, const int32_t* src, const int32_t* idx, int64_t nnz
         else
             radix_sort_u64(c, reinterpret_cast<uint64_t*>(keys.p), reinterpret_cast<uint64_t*>(tmp.p), m,
                            2 * bb);
-        hipLaunchKernelGGL((k_flag_unique<K>), grid_for(m), dim3(kThreads), 0, c->stream, keys.p, m,
+        hipLaunchKernelGGL((k_flag_unique<K>), grid_for(m), dim3(kThreads), 0, c->stream, keys.p, m, sent,
                            flag.p);
         GOSH_HIP(hipGetLastError());
         scan_i32_to_i64(c, flag.p, pos.p, m, &nnz_next);
