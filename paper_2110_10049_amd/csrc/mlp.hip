@@ -40,7 +40,8 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 constexpr float kRsqrt2 = 0.70710678118654752f;
 constexpr float kRsqrt2Pi = 0.39894228040143268f;
 constexpr int kLdsLimitFrags = 160;        // 16x32 BF16 fragments (1 KiB each) that fit in LDS
-constexpr int kFwdThreads = 512;
+constexpr int kFwdThreads = 512;      // forward blocks for d = 256 (two row tiles per wave)
+constexpr int kFwdThreadsWide = 1024; // forward blocks for d <= 128 (one row tile per wave)
 constexpr int kTrainThreads = 256;
 
 // ------------------------------------------------------------ shapes
@@ -222,8 +223,8 @@ __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ 
                 const float z = a1[m][nt][i] + bb[i];
                 float ez;
                 const float lo = phi_lower(z, ez);        // Phi(-|z|)
-                const float zl = z * lo;
-                g[i] = z >= 0.0f ? z - zl : zl;            // z Phi(z)
+                // z Phi(z) = max(z, 0) - |z| Phi(-|z|) for either sign of z
+                g[i] = fmaf(-fabsf(z), lo, fmaxf(z, 0.0f));
                 keep(nt, h0 + i, z, lo, ez);
             }
             hb[nt][2 * m] = pack2(g[0], g[1]);
@@ -235,8 +236,8 @@ __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ 
 // ------------------------------------------------------------ inference
 // Every wave loops over 16*NT-row tiles; W1 and W2 fragments are staged in
 // LDS once per workgroup when they fit (WLDS), else read through L2.
-template <int D, int H, int NT, bool BF16, bool WLDS>
-__global__ __launch_bounds__(kFwdThreads) void k_forward(RowSrc S, const u32x4* __restrict__ W1f,
+template <int D, int H, int NT, bool BF16, bool WLDS, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_forward(RowSrc S, const u32x4* __restrict__ W1f,
                                                          const u32x4* __restrict__ W2f,
                                                          const float* __restrict__ b1,
                                                          const float* __restrict__ b2, void* __restrict__ out,
@@ -820,10 +821,15 @@ void mlp_prolong(Ctx* c, const gosh_mlp* M, const Level& fine, int64_t n_coarse,
     const int ncu = num_cus(c->device);
     dispatch(M->d, M->hidden, [&](auto dd, auto hh) {
         constexpr int D = decltype(dd)::value, H = decltype(hh)::value;
-        constexpr int NT = D >= 256 ? 1 : 2;
+        // d <= 128: one 16-row tile per wave and 16 waves per workgroup, so
+        // that each SIMD holds 4 waves against the one copy of the weights in
+        // LDS (the GELU between the two products needs waves to hide its
+        // latency); d = 256 keeps 8 waves of one tile each
+        constexpr int NT = 1;
+        constexpr int T = D >= 256 ? kFwdThreads : kFwdThreadsWide;
         constexpr bool WL = fits_lds<D, H>();
         const int64_t ntiles = ceil_div(fine.n, 16 * NT);
-        const int64_t per_block = kFwdThreads / 64;
+        const int64_t per_block = T / 64;
         const unsigned blocks =
             static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(ntiles, per_block), int64_t(ncu) * (WL ? 1 : 2))));
         const u32x4* w1 = reinterpret_cast<const u32x4*>(M->w1f);
@@ -831,10 +837,10 @@ void mlp_prolong(Ctx* c, const gosh_mlp* M, const Level& fine, int64_t n_coarse,
         const float* b1 = M->master + Shape{D, H}.off_b1();
         const float* b2 = M->master + Shape{D, H}.off_b2();
         if (dt == GOSH_BF16)
-            hipLaunchKernelGGL((k_forward<D, H, NT, true, WL>), dim3(blocks), dim3(kFwdThreads), 0, c->stream, S, w1, w2,
+            hipLaunchKernelGGL((k_forward<D, H, NT, true, WL, T>), dim3(blocks), dim3(T), 0, c->stream, S, w1, w2,
                                b1, b2, fine_emb, ntiles);
         else
-            hipLaunchKernelGGL((k_forward<D, H, NT, false, WL>), dim3(blocks), dim3(kFwdThreads), 0, c->stream, S, w1,
+            hipLaunchKernelGGL((k_forward<D, H, NT, false, WL, T>), dim3(blocks), dim3(T), 0, c->stream, S, w1,
                                w2, b1, b2, fine_emb, ntiles);
     });
     GOSH_HIP(hipGetLastError());
