@@ -102,7 +102,7 @@ def parse():
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-sample-epochs", type=int, default=4)
+    ap.add_argument("--cpu-sample-epochs", type=int, default=10)
     ap.add_argument("--mlp-steps", type=int, default=2000, help="Adam steps of the prolongation network")
     ap.add_argument("--mlp-budgets", default="75,150,300,600", help="epoch budgets of the learned-vs-copy sweep")
     ap.add_argument("--mlp-no-eval", action="store_true", help="skip the link-prediction sweep (kernel timing only)")
