@@ -207,7 +207,10 @@ gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
  * (sample rows once per update, the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
  * lr finite and >= 0.  `tag` (24 bits) separates independent random
  * streams.  If `updates_dev` is not NULL, the number of UpdateEmbed calls
- * executed is added to *updates_dev (device uint64).  Asynchronous. */
+ * executed is added to *updates_dev (device uint64).  An epoch is one
+ * launch with up to 16 lanes per source (32 at d = 256): a level whose
+ * vertices times lanes reach 2^32 - 4096 (268M vertices at d = 128)
+ * returns GOSH_E_UNSUPPORTED outside deterministic mode.  Asynchronous. */
 gosh_status gosh_train(gosh_ctx* ctx, const gosh_levels* lv, int32_t level, void* emb,
                        gosh_dtype dt, int32_t d, int32_t epochs, float lr, int32_t k,
                        uint32_t tag, uint64_t* updates_dev);

@@ -127,13 +127,16 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs P) {
         // (slot i -> vertex i mod m, sample i div m) keeps the B visits of one
         // source apart instead of in the same wave, where their atomic
         // commits to the one source row would serialize.
+        // The slots run grid-stride, so a pool may hold more entries than
+        // one launch has lanes.
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-        int64_t i = wave * G + grp;
-        const bool s1 = i >= P.f0;
-        if (s1) i -= P.f0;
-        const int64_t full = s1 ? P.f1 : P.f0;
-        const int64_t m = full / P.B;
-        if (i < full) {
+        const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
+        for (int64_t slot = wave * G + grp; slot < P.f0 + P.f1; slot += stride) {
+            int64_t i = slot;
+            const bool s1 = i >= P.f0;
+            if (s1) i -= P.f0;
+            const int64_t full = s1 ? P.f1 : P.f0;
+            const int64_t m = full / P.B;
             const int64_t e = (i % m) * P.B + i / m;
             if (e < (s1 ? P.n1 : P.n0)) pair_visit<BF16, D, KMAX>(P, s1 ? P.n0 + e : e, gl);
         }
@@ -148,7 +151,8 @@ void launch_pair(const PairArgs& P, hipStream_t st, bool seq) {
     if (seq) {
         hipLaunchKernelGGL((k_pair<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, P);
     } else {
-        const int64_t blocks = std::max<int64_t>(1, ceil_div(P.f0 + P.f1, (kBlock / 64) * G));
+        const int64_t blocks =
+            std::min<int64_t>(std::max<int64_t>(1, ceil_div(P.f0 + P.f1, (kBlock / 64) * G)), int64_t(1) << 20);
         hipLaunchKernelGGL((k_pair<BF16, D, KMAX, false>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, P);
     }
 }

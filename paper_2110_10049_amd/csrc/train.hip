@@ -164,6 +164,20 @@ void check_train_args(gosh_dtype dt, int d, int k, float lr) {
     GOSH_REQUIRE(std::isfinite(lr) && lr >= 0.0f, GOSH_E_INVALID_ARG, "lr must be finite and >= 0");
 }
 
+// Lanes serving one row (Lanes::kL) for a runtime dtype and d.
+template <bool BF16>
+int lanes_for(int d) {
+    switch (d) {
+        case 8: return Lanes<BF16, 8>::kL;
+        case 16: return Lanes<BF16, 16>::kL;
+        case 32: return Lanes<BF16, 32>::kL;
+        case 64: return Lanes<BF16, 64>::kL;
+        case 128: return Lanes<BF16, 128>::kL;
+        default: return Lanes<BF16, 256>::kL;
+    }
+}
+int lanes_per_row(gosh_dtype dt, int d) { return dt == GOSH_BF16 ? lanes_for<true>(d) : lanes_for<false>(d); }
+
 TrainParams base_params(Ctx* c, int32_t level, uint32_t tag) {
     TrainParams P{};
     P.key0 = static_cast<uint32_t>(c->seed);
@@ -194,7 +208,14 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     GOSH_REQUIRE(fn, GOSH_E_INVALID_ARG, "unsupported training shape");
     // epochs run one launch each (Section 3.1), unless the context lets
     // `overlap` epochs share a launch on levels of at least overlap_min vertices
-    const int span = (!c->deterministic && c->overlap > 1 && L.n >= c->overlap_min) ? c->overlap : 1;
+    int span = (!c->deterministic && c->overlap > 1 && L.n >= c->overlap_min) ? c->overlap : 1;
+    // one launch covers n * span sources with L lanes each; a 1-D launch
+    // holds fewer than 2^32 lanes
+    const int64_t lanes_per_source = lanes_per_row(dt, d);
+    constexpr int64_t kMaxLanes = (int64_t(1) << 32) - 4096;
+    GOSH_REQUIRE(c->deterministic || L.n * lanes_per_source <= kMaxLanes, GOSH_E_UNSUPPORTED,
+                 "level too large for one epoch launch at this d");
+    while (span > 1 && L.n * span * lanes_per_source > kMaxLanes) span /= 2;
     P.span = 1;
     P.e_total = epochs;
     P.lr0 = lr;

@@ -35,6 +35,7 @@ using namespace train_detail;
 
 constexpr int kWalkThreads = 256;
 constexpr int kMaxWalkLen = 1024;
+constexpr int64_t kMaxGridBlocks = int64_t(1) << 20;   // 2^28 lanes per launch, far below the 2^32 limit
 constexpr int kLdsSteps = 16;     // walks of up to 15 steps are counted from LDS (16 KiB per block)
 
 struct WalkArgs {
@@ -184,9 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_train(WalkTrain T) {
             __threadfence();
         }
     } else {
+        // grid-stride over the ranks: an epoch can hold more ranks than one
+        // launch has lanes (n P up to 2^32)
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-        const int64_t r = wave * G + grp;
-        if (r < T.m) walk_visit<BF16, D, KMAX>(T, r, gl);
+        const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
+        for (int64_t r = wave * G + grp; r < T.m; r += stride) walk_visit<BF16, D, KMAX>(T, r, gl);
     }
 }
 
@@ -198,7 +201,7 @@ void launch_walk(const WalkTrain& T, hipStream_t st, bool seq) {
     if (seq) {
         hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, T);
     } else {
-        const int64_t blocks = ceil_div(T.m, (kBlock / 64) * G);
+        const int64_t blocks = std::min<int64_t>(ceil_div(T.m, (kBlock / 64) * G), kMaxGridBlocks);
         hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, false>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock),
                            0, st, T);
     }
