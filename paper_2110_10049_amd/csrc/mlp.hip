@@ -39,6 +39,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr float kRsqrt2 = 0.70710678118654752f;
 constexpr float kRsqrt2Pi = 0.39894228040143268f;
+constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kLdsLimitFrags = 160;        // 16x32 BF16 fragments (1 KiB each) that fit in LDS
 constexpr int kFwdThreads = 512;      // forward blocks for d = 256 (two row tiles per wave)
 constexpr int kFwdThreadsWide = 1024; // forward blocks for d <= 128 (one row tile per wave)
@@ -172,8 +173,11 @@ __device__ __forceinline__ void load_x(const RowSrc& S, int64_t base, int lane, 
             } else {
                 deg = S.deg[r];
             }
-            fdeg = log1pf(static_cast<float>(deg));
-            fcs = logf(static_cast<float>(S.clsz[cid[nt]]));
+            // ln(deg + 1) and ln(clsz) of integers >= 1 through the hardware
+            // base-2 logarithm (a few FP32 ulps; the features are rounded
+            // to BF16 next); a degree fits in 32 bits (indices are int32)
+            fdeg = __builtin_amdgcn_logf(static_cast<float>(static_cast<int32_t>(deg) + 1)) * kLn2;
+            fcs = __builtin_amdgcn_logf(static_cast<float>(S.clsz[cid[nt]])) * kLn2;
         }
 #pragma unroll
         for (int kb = 0; kb < KB1; ++kb) {
@@ -190,23 +194,28 @@ __device__ __forceinline__ void load_x(const RowSrc& S, int64_t base, int lane, 
 }
 
 // One 32-wide hidden block: layer 1 for hidden rows 32 kb2 .. +31 and the
-// GELU, returned as layer-2 B fragments hb[nt] (permuted K order).  z,
-// Phi(-|z|) and exp(-z^2/2) are handed to `keep` for the backward pass.
-template <int D, int H, int NT, class WPtr, class Keep>
-__device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ b1, int kb2, int lane,
+// GELU, returned as layer-2 B fragments hb[nt] (permuted K order).  w1b
+// points at the block's 2 * (D/32 + 1) W1 fragments and b1b at its 32
+// biases.  z, Phi(-|z|) and exp(-z^2/2) are handed to `keep` for the
+// backward pass.
+template <int D, int H, int NT, class WPtr, class BPtr, class Keep>
+__device__ __forceinline__ void hidden_block(WPtr w1b, BPtr b1b, int kb2, int lane,
                                              const u32x4 (&xf)[NT][D / 32 + 1], u32x4 (&hb)[NT], Keep&& keep) {
     constexpr int KB1 = D / 32 + 1;
     const int q = lane >> 4;
+    // the accumulators start at the bias, so z needs no add after the product
     f32x4 a1[2][NT];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < 2; ++m) {
+        const f32x4 bb = *reinterpret_cast<const f32x4*>(b1b + m * 16 + 4 * q);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) a1[m][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NT; ++nt) a1[m][nt] = bb;
+    }
 #pragma unroll
     for (int kb = 0; kb < KB1; ++kb) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-            const u32x4 w = w1[((2 * kb2 + m) * KB1 + kb) * 64 + lane];
+            const u32x4 w = w1b[(m * KB1 + kb) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) a1[m][nt] = mfma(w, xf[nt][kb], a1[m][nt]);
         }
@@ -214,17 +223,18 @@ __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ 
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int h0 = (2 * kb2 + m) * 16 + 4 * q;
-        const f32x4 bb = *reinterpret_cast<const f32x4*>(b1 + h0);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             float g[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float z = a1[m][nt][i] + bb[i];
+                const float z = a1[m][nt][i];
                 float ez;
                 const float lo = phi_lower(z, ez);        // Phi(-|z|)
-                // z Phi(z) = max(z, 0) - |z| Phi(-|z|) for either sign of z
-                g[i] = fmaf(-fabsf(z), lo, fmaxf(z, 0.0f));
+                // z Phi(z) = max(z, 0) - |z| Phi(-|z|) for either sign of z;
+                // max(z, 0) as a median with a finite bound, one instruction
+                // on the MFMA result with no canonicalising copy first
+                g[i] = fmaf(-fabsf(z), lo, __builtin_amdgcn_fmed3f(z, 0.0f, 3.0e38f));
                 keep(nt, h0 + i, z, lo, ez);
             }
             hb[nt][2 * m] = pack2(g[0], g[1]);
@@ -234,61 +244,108 @@ __device__ __forceinline__ void hidden_block(WPtr w1, const float* __restrict__ 
 }
 
 // ------------------------------------------------------------ inference
-// Every wave loops over 16*NT-row tiles; W1 and W2 fragments are staged in
-// LDS once per workgroup when they fit (WLDS), else read through L2.
+// Every wave loops over 16*NT-row tiles; W1, W2 and b1 are staged in LDS
+// once per workgroup when they fit (WLDS), else read through L2.  The LDS
+// copy is grouped by hidden block: W1 fragments, W2 fragments and biases of
+// one block lie together, so each operand read is a constant offset from
+// one block address.
 template <int D, int H, int NT, bool BF16, bool WLDS, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_forward(RowSrc S, const u32x4* __restrict__ W1f,
                                                          const u32x4* __restrict__ W2f,
                                                          const float* __restrict__ b1,
                                                          const float* __restrict__ b2, void* __restrict__ out,
                                                          int64_t ntiles) {
-    constexpr int KB1 = D / 32 + 1, KB2 = H / 32, MT1 = H / 16, MT2 = D / 16;
-    constexpr int NF1 = MT1 * KB1 * 64, NF2 = MT2 * KB2 * 64, NB = (H + D) / 4;
-    __shared__ u32x4 lds[WLDS ? NF1 + NF2 + NB : 1];
-    const u32x4* w1 = W1f;
-    const u32x4* w2 = W2f;
-    const float* bias1 = b1;
+    constexpr int KB1 = D / 32 + 1, KB2 = H / 32, MT2 = D / 16;
+    constexpr int W1B = 2 * KB1 * 64;               // W1 fragments of one hidden block (u32x4)
+    constexpr int BLK = W1B + MT2 * 64 + 8;         // + its W2 fragments + 32 biases
+    __shared__ u32x4 lds[WLDS ? KB2 * BLK + D / 4 : 1];
     const float* bias2 = b2;
     if constexpr (WLDS) {
-        for (int i = threadIdx.x; i < NF1; i += blockDim.x) lds[i] = W1f[i];
-        for (int i = threadIdx.x; i < NF2; i += blockDim.x) lds[NF1 + i] = W2f[i];
-        float* lb = reinterpret_cast<float*>(lds + NF1 + NF2);
-        for (int i = threadIdx.x; i < H + D; i += blockDim.x) lb[i] = i < H ? b1[i] : b2[i - H];
-        __syncthreads();
-        w1 = lds;
-        w2 = lds + NF1;
-        bias1 = lb;
-        bias2 = lb + H;
+        for (int i = threadIdx.x; i < KB2 * BLK; i += blockDim.x) {
+            const int b = i / BLK, o = i - b * BLK;
+            u32x4 v;
+            if (o < W1B) {
+                v = W1f[b * W1B + o];
+            } else if (o < W1B + MT2 * 64) {
+                const int f = o - W1B;
+                v = W2f[((f >> 6) * KB2 + b) * 64 + (f & 63)];
+            } else {
+                v = *reinterpret_cast<const u32x4*>(b1 + b * 32 + (o - W1B - MT2 * 64) * 4);
+            }
+            lds[i] = v;
+        }
+        float* lb2 = reinterpret_cast<float*>(lds + KB2 * BLK);
+        for (int i = threadIdx.x; i < D; i += blockDim.x) lb2[i] = b2[i];
+        bias2 = lb2;
     }
+    // BF16 rows: the residual c is added by one MFMA per output tile, with a
+    // 0/1 selection matrix as the A operand and the X fragment that already
+    // holds c as the B operand: tile mt with sel[mt & 1] and X block mt / 2
+    // gives c[mt * 16 + m] (exact products, FP32 accumulation)
+    __shared__ u32x4 lsel[BF16 ? 128 : 1];
+    if constexpr (BF16) {
+        for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+            const int sel = (i >> 6) * 16 + (i & 15), k0 = 8 * ((i & 63) >> 4);
+            u32x4 v;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                v[w] = (k0 + 2 * w == sel ? 0x3F80u : 0u) | (k0 + 2 * w + 1 == sel ? 0x3F800000u : 0u);
+            lsel[i] = v;
+        }
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
     const int nw = blockDim.x >> 6;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * nw;
     int64_t t = static_cast<int64_t>(blockIdx.x) * nw + (threadIdx.x >> 6);
-    // the gather of a tile's X is issued one tile ahead
+    // no prefetch of the next tile's X: its registers would spill, and the
+    // other waves of the SIMD cover the gather
     u32x4 xf[NT][KB1];
     int64_t cid[NT];
     bool ok[NT];
-    if (t < ntiles) load_x<D, NT, BF16>(S, t * (16 * NT), lane, xf, cid, ok);
     for (; t < ntiles; t += stride) {
         const int64_t base = t * (16 * NT);
-        u32x4 xn[NT][KB1];
-        int64_t cn[NT];
-        bool okn[NT];
-        if (t + stride < ntiles) load_x<D, NT, BF16>(S, (t + stride) * (16 * NT), lane, xn, cn, okn);
+        load_x<D, NT, BF16>(S, t * (16 * NT), lane, xf, cid, ok);
+        // the output accumulators start at b2
         f32x4 acc[MT2][NT];
 #pragma unroll
-        for (int mt = 0; mt < MT2; ++mt)
+        for (int mt = 0; mt < MT2; ++mt) {
+            const f32x4 bb = *reinterpret_cast<const f32x4*>(bias2 + mt * 16 + 4 * q);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = bb;
+        }
 #pragma unroll 1
         for (int kb2 = 0; kb2 < KB2; ++kb2) {
+            const u32x4* w1b;
+            const u32x4* w2b;
+            const float* b1b;
+            int w2s;
+            if constexpr (WLDS) {
+                w1b = lds + kb2 * BLK;
+                w2b = w1b + W1B;
+                w2s = 64;
+                b1b = reinterpret_cast<const float*>(w2b + MT2 * 64);
+            } else {
+                w1b = W1f + kb2 * W1B;
+                w2b = W2f + kb2 * 64;
+                w2s = KB2 * 64;
+                b1b = b1 + kb2 * 32;
+            }
             u32x4 hb[NT];
-            hidden_block<D, H, NT>(w1, bias1, kb2, lane, xf, hb, [](int, int, float, float, float) {});
+            hidden_block<D, H, NT>(w1b, b1b, kb2, lane, xf, hb, [](int, int, float, float, float) {});
 #pragma unroll
             for (int mt = 0; mt < MT2; ++mt) {
-                const u32x4 w = w2[(mt * KB2 + kb2) * 64 + lane];
+                const u32x4 w = w2b[mt * w2s + lane];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma(w, hb[nt], acc[mt][nt]);
+            }
+        }
+        if constexpr (BF16) {
+#pragma unroll
+            for (int mt = 0; mt < MT2; ++mt) {
+                const u32x4 sw = lsel[(mt & 1) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma(sw, xf[nt][mt >> 1], acc[mt][nt]);
             }
         }
 #pragma unroll
@@ -298,20 +355,14 @@ __global__ __launch_bounds__(THREADS) void k_forward(RowSrc S, const u32x4* __re
 #pragma unroll
             for (int mt = 0; mt < MT2; ++mt) {
                 const int f0 = mt * 16 + 4 * q;
-                const f32x4 c = load_row4<BF16>(S.coarse, cid[nt], D, f0);
-                const f32x4 bb = *reinterpret_cast<const f32x4*>(bias2 + f0);
-                f32x4 y;
+                f32x4 y = acc[mt][nt];
+                if constexpr (!BF16) {   // FP32 rows: the residual in full precision
+                    const f32x4 c = load_row4<BF16>(S.coarse, cid[nt], D, f0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) y[i] = c[i] + (acc[mt][nt][i] + bb[i]);
+                    for (int i = 0; i < 4; ++i) y[i] += c[i];
+                }
                 store_row4<BF16>(out, r, D, f0, y);
             }
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            cid[nt] = cn[nt];
-            ok[nt] = okn[nt];
-#pragma unroll
-            for (int kb = 0; kb < KB1; ++kb) xf[nt][kb] = xn[nt][kb];
         }
     }
 }
@@ -371,7 +422,8 @@ __global__ __launch_bounds__(kTrainThreads) void k_train_fwd(RowSrc S, const voi
 #pragma unroll 1
     for (int kb2 = 0; kb2 < KB2; ++kb2) {
         u32x4 hb[NT];
-        hidden_block<D, H, NT>(W1f, b1, kb2, lane, xf, hb, [&](int nt, int h, float z, float lo, float ez) {
+        hidden_block<D, H, NT>(W1f + kb2 * 2 * KB1 * 64, b1 + kb2 * 32, kb2, lane, xf, hb,
+                               [&](int nt, int h, float z, float lo, float ez) {
             const float P = z >= 0.0f ? 1.0f - lo : lo;
             T.gp[static_cast<int64_t>(h) * bp + base + nt * 16 + r16] = fmaf(z * ez, kRsqrt2Pi, P);   // GELU'(z)
         });
@@ -663,7 +715,7 @@ bool supported(int d, int h) {
 
 template <int D, int H>
 constexpr bool fits_lds() {   // weight fragments plus the biases (under one fragment)
-    return (H / 16) * (D / 32 + 1) + (D / 16) * (H / 32) + 1 <= kLdsLimitFrags;
+    return (H / 16) * (D / 32 + 1) + (D / 16) * (H / 32) + 1 + 2 <= kLdsLimitFrags;   // + 2 selection fragments
 }
 
 int num_cus(int device) {
