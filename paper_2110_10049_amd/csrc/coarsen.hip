@@ -38,6 +38,34 @@ inline dim3 grid_for(int64_t items, int64_t per_block = kThreads) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < (N); \
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
 
+// Kernels that fold into one global counter: at most this many blocks, and
+// one atomic per block (same-address atomics serialise at one L2 channel,
+// one per wave cost ~80 us on a 93k-vertex level)
+constexpr int64_t kReduceBlocks = 2048;
+inline dim3 grid_reduce(int64_t items, int64_t per_block = kThreads) {
+    return dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(std::max<int64_t>(items, 1), per_block),
+                                                        kReduceBlocks)));
+}
+
+// Block sum (op 0) or maximum (op 1) of v, added / maxed into *dst by thread
+// 0; every thread of the block calls it (blocks of at most kThreads).
+template <int OP>
+__device__ __forceinline__ void block_fold(unsigned long long* dst, unsigned long long v) {
+    __shared__ unsigned long long part[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(v, o, 64);
+        v = OP == 0 ? v + t : (v > t ? v : t);
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = part[0];
+        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) r = OP == 0 ? r + part[w] : (r > part[w] ? r : part[w]);
+        if (OP == 0 && r) atomicAdd(dst, r);
+        if (OP == 1) atomicMax(dst, r);
+    }
+}
+
 // ---------------------------------------------------------------- degrees, order
 template <class Off>
 __global__ void k_degree(const Off* off, int64_t n, int64_t nnz, uint8_t* light,
@@ -50,15 +78,11 @@ __global__ void k_degree(const Off* off, int64_t n, int64_t nnz, uint8_t* light,
         mx = mx > static_cast<unsigned long long>(d) ? mx : static_cast<unsigned long long>(d);
         iso += (d == 0);
     }
-    // wave-level reduction, then one atomic per wave
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long t = __shfl_xor(mx, o, 64);
-        mx = mx > t ? mx : t;
-        iso += __shfl_xor(iso, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (maxdeg) atomicMax(maxdeg, mx);
-        if (isolated) atomicAdd(isolated, iso);
+    // block-level reductions, one atomic per block (pointer tests are uniform)
+    if (maxdeg) block_fold<1>(maxdeg, mx);
+    if (isolated) {
+        __syncthreads();
+        block_fold<0>(isolated, iso);
     }
 }
 
@@ -136,8 +160,7 @@ __global__ void k_round(int64_t n, const int64_t* lstart, const int32_t* lower, 
         else if (!pending) state[v] = kIn;
         else ++cnt;
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(undecided, cnt);
+    block_fold<0>(undecided, cnt);
 }
 
 // The same decision with one wave per vertex, for dense levels whose
@@ -168,7 +191,7 @@ __global__ void k_round_wave(int64_t n, const int64_t* lstart, const int32_t* lo
             else ++cnt;
         }
     }
-    if (lane == 0 && cnt) atomicAdd(undecided, cnt);
+    block_fold<0>(undecided, cnt);   // cnt is lane 0's; the other lanes hold 0
 }
 
 __global__ void k_hub_flags_by_rank(const uint32_t* perm, int64_t n, const uint8_t* state, int32_t* hf) {
@@ -535,10 +558,10 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
         GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
         GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
         if (dense)
-            hipLaunchKernelGGL(k_round_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
-                               lower.p, state.p, scratch_u64(c, 1));
+            hipLaunchKernelGGL(k_round_wave, grid_reduce(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
+                               lstart.p, lower.p, state.p, scratch_u64(c, 1));
         else
-            hipLaunchKernelGGL(k_round, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
+            hipLaunchKernelGGL(k_round, grid_reduce(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
                                scratch_u64(c, 1));
         GOSH_HIP(hipGetLastError());
         if (read_u64(c, scratch_u64(c, 1)) == 0) break;
@@ -610,7 +633,7 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     DevBuf<uint8_t> light(c, n);
     DevBuf<int64_t> deg(c, n);
     GOSH_HIP(hipMemsetAsync(scratch_u64(c, 0), 0, 8, c->stream));
-    hipLaunchKernelGGL((k_degree<Off>), grid_for(n), dim3(kThreads), 0, c->stream, off, n, nnz,
+    hipLaunchKernelGGL((k_degree<Off>), grid_reduce(n), dim3(kThreads), 0, c->stream, off, n, nnz,
                        light.p, deg.p, scratch_u64(c, 0), nullptr);
     GOSH_HIP(hipGetLastError());
     DevBuf<uint32_t> key(c, n), key_tmp(c, n), perm(c, n), perm_tmp(c, n);
@@ -671,11 +694,11 @@ int64_t count_isolated(Ctx* c, const Level& L) {
     if (L.n > 0) {
         GOSH_HIP(hipMemsetAsync(scratch_u64(c, 2), 0, 8, c->stream));
         if (L.off64)
-            hipLaunchKernelGGL((k_degree<int64_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
+            hipLaunchKernelGGL((k_degree<int64_t>), grid_reduce(L.n), dim3(kThreads), 0, c->stream,
                                static_cast<const int64_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
                                scratch_u64(c, 2));
         else
-            hipLaunchKernelGGL((k_degree<int32_t>), grid_for(L.n), dim3(kThreads), 0, c->stream,
+            hipLaunchKernelGGL((k_degree<int32_t>), grid_reduce(L.n), dim3(kThreads), 0, c->stream,
                                static_cast<const int32_t*>(L.offsets), L.n, L.nnz, nullptr, nullptr, nullptr,
                                scratch_u64(c, 2));
         GOSH_HIP(hipGetLastError());
