@@ -211,3 +211,35 @@ def test_train_argument_errors(gctx):
         G.gosh_train(gctx, lv, 0, torch.zeros((64, 24), device="cuda"), 1, 0.1, 1)   # d = 24
     with pytest.raises(G.GoshError):
         G.gosh_train(gctx, lv, 3, M, 1, 0.1, 1)                                      # no level 3
+
+
+def test_full_scale20_bench_configuration(gctx, orc):
+    """The launch the benchmark times, at full size: level 0 of the scale-20
+    R-MAT train graph (614k sources), k = 3, d = 128, BF16 rows, plain
+    negative stores.  The samples of 20,000 sampled sources (and the first and
+    last) equal the oracle's draws bit for bit; an epoch at lr = 0 leaves every
+    row bit-identical and executes exactly the oracle's update count."""
+    from paper_2110_10049_amd import gosh as G
+    sp = train_split(20, 16)
+    n, k, d, epoch = sp.n, 3, 128, 5
+    print(f"[full scale 20] n={n}", flush=True)
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(sp.offsets, sp.indices))
+    got = G.gosh_draw_samples(gctx, lv, 0, epoch, k).cpu().numpy()
+    rng = np.random.default_rng(9)
+    srcs = np.unique(np.concatenate([rng.integers(0, n, 20000), [0, n - 1]]))
+    want = np.stack([orc.draw_samples(sp.offsets, sp.indices, SEED, 0, 0, epoch, int(s), k) for s in srcs])
+    assert np.array_equal(got[srcs], want)
+
+    M0 = torch.from_numpy(init_rows(n, d, 3)).to(torch.bfloat16).cuda()
+    M = M0.clone()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gctx.set_plain_negatives(65536)
+    try:
+        G.gosh_train(gctx, lv, 0, M, 1, 0.0, k, 0, cnt)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_negatives(0)
+    assert torch.equal(M.view(torch.int16), M0.view(torch.int16))
+    # the update count does not depend on d: the oracle runs with 8-wide rows
+    upd = orc.train(sp.offsets, sp.indices, np.zeros((n, 8)), 1, 0.0, k, SEED)
+    assert int(cnt.item()) == upd
