@@ -73,7 +73,7 @@ def _check_close(Yg, Y, scale, ferr, bf16_out):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("d,H", [(32, 64), (128, 256), (256, 128), (64, 128)])
+@pytest.mark.parametrize("d,H", [(32, 64), (128, 256), (256, 128), (64, 128), (256, 256)])
 def test_prolong_matches_reference(gctx, orc, dtype, d, H):
     from paper_2110_10049_amd import gosh as G
     sp = train_split(12, 16)
