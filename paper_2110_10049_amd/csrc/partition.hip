@@ -107,8 +107,30 @@ __device__ __forceinline__ void pair_visit(const PairArgs& P, int64_t e, int gl)
                                        opp, P.key0, P.key1, P.updates, gl);
 }
 
-// SEQ: one wave walks the entries in pool order (deterministic mode).
-template <bool BF16, int D, int KMAX, bool SEQ>
+// Launch shapes: one wave walks the entries in pool order (deterministic
+// mode), one slot per lane group when one launch covers the pool, else a
+// grid-stride loop (a pool may hold more entries than one launch has lanes).
+// The loop is its own instantiation: inside a loop the visit holds more
+// registers (100 against 84 VGPRs, 5 instead of 6 waves per SIMD).
+enum PairShape { kPairSeq = 0, kPairOnce = 1, kPairStride = 2 };
+constexpr int64_t kPairMaxBlocks = int64_t(1) << 20;
+
+// A vertex owns B consecutive entries of its side; visiting b-major (slot
+// i -> vertex i mod m, sample i div m) keeps the B visits of one source apart
+// instead of in the same wave, where their atomic commits to the one source
+// row would serialize.
+template <bool BF16, int D, int KMAX>
+__device__ __forceinline__ void pair_slot(const PairArgs& P, int64_t slot, int gl) {
+    int64_t i = slot;
+    const bool s1 = i >= P.f0;
+    if (s1) i -= P.f0;
+    const int64_t full = s1 ? P.f1 : P.f0;
+    const int64_t m = full / P.B;
+    const int64_t e = (i % m) * P.B + i / m;
+    if (e < (s1 ? P.n1 : P.n0)) pair_visit<BF16, D, KMAX>(P, s1 ? P.n0 + e : e, gl);
+}
+
+template <bool BF16, int D, int KMAX, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs P) {
     constexpr int L = Lanes<BF16, D>::kL;
     constexpr int G = Lanes<BF16, D>::kG;
@@ -117,28 +139,19 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs P) {
     const int64_t total = P.n0 + P.n1;
     if (P.updates && blockIdx.x == 0 && threadIdx.x == 0)
         atomicAdd(P.updates, static_cast<unsigned long long>(total) * static_cast<unsigned long long>(1 + P.k));
-    if constexpr (SEQ) {
+    if constexpr (SHAPE == kPairSeq) {
         for (int64_t e = 0; e < total; ++e) {
             if (grp == 0) pair_visit<BF16, D, KMAX>(P, e, gl);
             __threadfence();
         }
     } else {
-        // A vertex owns B consecutive entries of its side; visiting b-major
-        // (slot i -> vertex i mod m, sample i div m) keeps the B visits of one
-        // source apart instead of in the same wave, where their atomic
-        // commits to the one source row would serialize.
-        // The slots run grid-stride, so a pool may hold more entries than
-        // one launch has lanes.
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-        const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
-        for (int64_t slot = wave * G + grp; slot < P.f0 + P.f1; slot += stride) {
-            int64_t i = slot;
-            const bool s1 = i >= P.f0;
-            if (s1) i -= P.f0;
-            const int64_t full = s1 ? P.f1 : P.f0;
-            const int64_t m = full / P.B;
-            const int64_t e = (i % m) * P.B + i / m;
-            if (e < (s1 ? P.n1 : P.n0)) pair_visit<BF16, D, KMAX>(P, s1 ? P.n0 + e : e, gl);
+        if constexpr (SHAPE == kPairOnce) {
+            const int64_t slot = wave * G + grp;
+            if (slot < P.f0 + P.f1) pair_slot<BF16, D, KMAX>(P, slot, gl);
+        } else {
+            const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
+            for (int64_t slot = wave * G + grp; slot < P.f0 + P.f1; slot += stride) pair_slot<BF16, D, KMAX>(P, slot, gl);
         }
     }
 }
@@ -149,12 +162,15 @@ template <bool BF16, int D, int KMAX>
 void launch_pair(const PairArgs& P, hipStream_t st, bool seq) {
     constexpr int G = Lanes<BF16, D>::kG;
     if (seq) {
-        hipLaunchKernelGGL((k_pair<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, P);
-    } else {
-        const int64_t blocks =
-            std::min<int64_t>(std::max<int64_t>(1, ceil_div(P.f0 + P.f1, (kBlock / 64) * G)), int64_t(1) << 20);
-        hipLaunchKernelGGL((k_pair<BF16, D, KMAX, false>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, P);
+        hipLaunchKernelGGL((k_pair<BF16, D, KMAX, kPairSeq>), dim3(1), dim3(64), 0, st, P);
+        return;
     }
+    const int64_t need = std::max<int64_t>(1, ceil_div(P.f0 + P.f1, (kBlock / 64) * G));
+    if (need <= kPairMaxBlocks)
+        hipLaunchKernelGGL((k_pair<BF16, D, KMAX, kPairOnce>), dim3(static_cast<unsigned>(need)), dim3(kBlock), 0, st, P);
+    else
+        hipLaunchKernelGGL((k_pair<BF16, D, KMAX, kPairStride>), dim3(static_cast<unsigned>(kPairMaxBlocks)), dim3(kBlock),
+                           0, st, P);
 }
 
 template <bool BF16, int D>

@@ -172,24 +172,34 @@ __device__ __forceinline__ void walk_visit(const WalkTrain& T, int64_t r, int gl
                                        T.key0, T.key1, T.updates, gl, T.plain_neg != 0);
 }
 
-template <bool BF16, int D, int KMAX, bool SEQ>
+// Launch shapes: one wave in rank order (deterministic mode), one rank per
+// lane group when one launch covers the epoch, else a grid-stride loop (an
+// epoch can hold more ranks than one launch has lanes, n P up to 2^32).  The
+// loop is its own instantiation: inside a loop the visit holds more registers
+// (137 against 112 VGPRs, 3 instead of 4 waves per SIMD).
+enum WalkShape { kWalkSeq = 0, kWalkOnce = 1, kWalkStride = 2 };
+
+template <bool BF16, int D, int KMAX, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_walk_train(WalkTrain T) {
     constexpr int L = Lanes<BF16, D>::kL;
     constexpr int G = Lanes<BF16, D>::kG;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
-    if constexpr (SEQ) {
+    if constexpr (SHAPE == kWalkSeq) {
         // one wave, ranks strictly in order
         for (int64_t r = 0; r < T.m; ++r) {
             if (grp == 0) walk_visit<BF16, D, KMAX>(T, r, gl);
             __threadfence();
         }
     } else {
-        // grid-stride over the ranks: an epoch can hold more ranks than one
-        // launch has lanes (n P up to 2^32)
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-        const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
-        for (int64_t r = wave * G + grp; r < T.m; r += stride) walk_visit<BF16, D, KMAX>(T, r, gl);
+        if constexpr (SHAPE == kWalkOnce) {
+            const int64_t r = wave * G + grp;
+            if (r < T.m) walk_visit<BF16, D, KMAX>(T, r, gl);
+        } else {
+            const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / 64) * G;
+            for (int64_t r = wave * G + grp; r < T.m; r += stride) walk_visit<BF16, D, KMAX>(T, r, gl);
+        }
     }
 }
 
@@ -199,12 +209,16 @@ template <bool BF16, int D, int KMAX>
 void launch_walk(const WalkTrain& T, hipStream_t st, bool seq) {
     constexpr int G = Lanes<BF16, D>::kG;
     if (seq) {
-        hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, true>), dim3(1), dim3(64), 0, st, T);
-    } else {
-        const int64_t blocks = std::min<int64_t>(ceil_div(T.m, (kBlock / 64) * G), kMaxGridBlocks);
-        hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, false>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock),
-                           0, st, T);
+        hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, kWalkSeq>), dim3(1), dim3(64), 0, st, T);
+        return;
     }
+    const int64_t need = ceil_div(T.m, (kBlock / 64) * G);
+    if (need <= kMaxGridBlocks)
+        hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, kWalkOnce>), dim3(static_cast<unsigned>(std::max<int64_t>(need, 1))),
+                           dim3(kBlock), 0, st, T);
+    else
+        hipLaunchKernelGGL((k_walk_train<BF16, D, KMAX, kWalkStride>), dim3(static_cast<unsigned>(kMaxGridBlocks)),
+                           dim3(kBlock), 0, st, T);
 }
 
 template <bool BF16, int D>
