@@ -77,7 +77,10 @@ gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream,
 /* Frees the context and all device memory it allocated, including that of
  * level hierarchies still alive; those can then only be destroyed. */
 gosh_status gosh_ctx_destroy(gosh_ctx* ctx);
-/* Orders subsequent work on `hip_stream` (NULL: the null stream). */
+/* Orders subsequent work on `hip_stream` (NULL: the null stream).  Waits
+ * for the work already queued on the previous stream first, since temporary
+ * blocks of asynchronous calls return to the context's cache when the call
+ * returns and may be handed out again on the new stream. */
 gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream);
 /* Blocks until all work enqueued by the context has finished. */
 gosh_status gosh_sync(gosh_ctx* ctx);

@@ -190,8 +190,15 @@ gosh_status gosh_ctx_destroy(gosh_ctx* ctx) {
 
 gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream) {
     if (!ctx) return GOSH_E_INVALID_ARG;
-    ctx->c.stream = static_cast<hipStream_t>(hip_stream);
-    return GOSH_OK;
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (s == ctx->c.stream) return GOSH_OK;
+    return guarded(ctx, [&] {
+        // blocks freed to the context's cache may still be read by work queued
+        // on the old stream; the new stream reuses them only after that work
+        set_device(&ctx->c);
+        GOSH_HIP(hipStreamSynchronize(ctx->c.stream));
+        ctx->c.stream = s;
+    });
 }
 
 gosh_status gosh_sync(gosh_ctx* ctx) {
