@@ -243,3 +243,29 @@ def test_full_scale20_bench_configuration(gctx, orc):
     # the update count does not depend on d: the oracle runs with 8-wide rows
     upd = orc.train(sp.offsets, sp.indices, np.zeros((n, 8)), 1, 0.0, k, SEED)
     assert int(cnt.item()) == upd
+
+
+def test_stream_switch_keeps_results(gctx):
+    """An epoch queued on a side stream, then the context moved back to the
+    default stream: the switch waits for the queued epoch, and its result
+    equals the same epoch run on the default stream (deterministic mode)."""
+    from paper_2110_10049_amd import gosh as G
+    sp = train_split(12, 16)
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(sp.offsets, sp.indices))
+    M0 = torch.from_numpy(init_rows(sp.n, 32, 3) * 8).cuda()
+    M, one = M0.clone(), M0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    gctx.set_deterministic(True)
+    try:
+        with torch.cuda.stream(side):
+            gctx.use_current_stream()
+            G.gosh_train(gctx, lv, 0, M, 1, 0.045, 3)
+        gctx.use_current_stream()
+        assert side.query()
+        G.gosh_train(gctx, lv, 0, one, 1, 0.045, 3)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_deterministic(False)
+        gctx.use_current_stream()
+    assert torch.equal(M, one)
