@@ -38,14 +38,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_bf16_traffic.md")
+WALK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_update_walk20_bf16_traffic.md")
 
 
-def measured_traffic():
-    """HBM bytes per level-0 launch from the committed counter summary, or
-    None if a source of the training kernel changed since it was measured."""
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per level-0 launch from a committed counter summary, or
+    None if a source of the measured kernel changed since it was measured."""
     import hashlib
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(path).read()
         keys = ("kernel_sources", "kernel_sources_sha256", "traffic_bytes_per_launch")
         fields = dict(l.strip().split(": ", 1) for l in txt.splitlines() if l.startswith("    ") and ": " in l
                       and l.strip().split(": ", 1)[0] in keys)
@@ -540,6 +541,19 @@ def big_workload(a):
     print(json.dumps(out), flush=True)
 
 
+def calibration_copy(mib):
+    """A plain device-to-device copy of `mib` MiB, for scaling the HBM
+    counters of a profiled run (0: none)."""
+    if not mib:
+        return
+    import torch
+    src_buf = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst_buf = torch.empty_like(src_buf)
+    dst_buf.copy_(src_buf)
+    torch.cuda.synchronize()
+    del src_buf, dst_buf
+
+
 def walk_workload(a):
     """Random-walk sampling (Section 3.2) in the multi-level pass: the scale-20
     R-MAT train graph of the default workload, d = 128, k = 3, one walk of
@@ -567,6 +581,7 @@ def walk_workload(a):
     sp = split_edges(*rmat_csr(scale, ef, seeds["graph"]), seeds["split"])
     n0, nnz = sp.n, len(sp.indices)
     log(f"graph ready: |V_train|={n0} nnz={nnz} ({time.time() - t0:.1f}s)")
+    calibration_copy(a.copy_calibration_mib)
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_plain_negatives(a.plain_neg_min)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
@@ -614,7 +629,10 @@ def walk_workload(a):
                    "levels": last.sizes, "schedule": last.schedule, "seeds": seeds,
                    "updates_per_step": updates // a.steps},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_walk_train level 0",
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": (measured_traffic(WALK_TRAFFIC_FILE)
+                                 if (L, W, a.plain_neg_min) == (10, 3, 65536) else None),
+                     "kernel": "k_walk_train level 0",
                      "bytes_per_launch": pairs0 * per_pair, "launch_us": round(launch_s * 1e6, 2)},
         "level0_sampling_ms_per_epoch": round(sample_ms / e0, 3),
     }
@@ -666,13 +684,7 @@ def main():
     sp = split_edges(off, idx, seeds["split"])
     log(f"graph ready: |V_train|={sp.n} nnz={len(sp.indices)} ({time.time() - t0:.1f}s)")
 
-    if a.copy_calibration_mib:
-        nb = a.copy_calibration_mib << 20
-        src_buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        dst_buf = torch.empty_like(src_buf)
-        dst_buf.copy_(src_buf)
-        torch.cuda.synchronize()
-        del src_buf, dst_buf
+    calibration_copy(a.copy_calibration_mib)
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     ctx.set_plain_negatives(a.plain_neg_min)
