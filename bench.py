@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_bf16_traffic.md")
 WALK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_update_walk20_bf16_traffic.md")
+MLP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "prolong_forward_mlp22_bf16_traffic.md")
 
 
 def measured_traffic(path=TRAFFIC_FILE):
@@ -219,6 +220,7 @@ def mlp_workload(a):
     d, H, k, lr, p, thr = 128, 256, 3, 0.045, 0.3, 100
     seeds = {"graph": 1, "split": 2, "init": 3, "philox": 4, "eval": 5, "mlp": 7}
     budgets = [int(x) for x in a.mlp_budgets.split(",")]
+    calibration_copy(a.copy_calibration_mib)
     ctx = G.Context(0, seed=seeds["philox"])
 
     def prepare(scale):
@@ -329,8 +331,9 @@ def mlp_workload(a):
                                f"k={k}, p={p}, lr={lr}", "levels": lv22.sizes(), "seeds": seeds,
                    "eval": "LR on 500k subsampled train pairs, AUC on 1M subsampled test pairs"},
         "roofline": {"bound": "mfma", "achieved": round(ach_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(ach_tf / 2500.0, 4), "traffic": None,
-                     "kernel": "k_forward (learned prolongation, level 0)"},
+                     "frac": round(ach_tf / 2500.0, 4), "traffic": measured_traffic(MLP_TRAFFIC_FILE),
+                     "kernel": "k_forward (learned prolongation, level 0)",
+                     "bytes_per_launch": n0 * bytes_row},
         "equal_auc": {"reference": ref, "bf16_learned_at": best,
                       "bf16_copy_min_epochs": min((r["epochs"] for r in copy_ok), default=None),
                       "time_ratio_fp32copy_over_bf16learned": round(ref["seconds"] / best["seconds"], 3),
