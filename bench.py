@@ -10,9 +10,10 @@ lr = 0.045, coarsening threshold 100.  The headline run stores rows in BF16
 (stochastic rounding, FP32 arithmetic); the same workload with FP32 rows is
 timed beside it, and both final embeddings are scored by link-prediction
 AUC on the held-out 20%.  Rows of negative samples are written with plain
-stores (the paper's lock-free writes) on levels of at least 65,536 vertices
-and with atomic adds elsewhere; positive and source rows always use atomic
-adds (--plain-neg-min 0: atomic adds everywhere).
+stores (the paper's lock-free writes) on levels of at least 262,144 vertices
+(level 0 of the scale-20 graph) and with atomic adds elsewhere; positive and
+source rows always use atomic adds (--plain-neg-min 0: atomic adds
+everywhere).
 
 value = executed UpdateEmbed calls (edge-samples) per second of step wall
 time.  roofline: the dominant kernel is the level-0 training epoch; its
@@ -98,7 +99,7 @@ def parse():
     ap.add_argument("--overlap-min", type=int, default=65536)
     ap.add_argument("--coarsen", default="exact", choices=["exact", "lock-skip"],
                     help="mapping step of the coarsening (lock-skip: the paper's parallel scheme)")
-    ap.add_argument("--plain-neg-min", type=int, default=65536,
+    ap.add_argument("--plain-neg-min", type=int, default=262144,
                     help="plain stores for negative rows on levels of at least this many vertices (0: atomic adds "
                          "everywhere)")
     ap.add_argument("--no-auc", action="store_true")

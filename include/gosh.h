@@ -144,6 +144,31 @@ gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int6
  * deterministic mode.  min_vertices >= 0. */
 gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices);
 
+/* Running loss of training (the objective of Section 2, the logistic loss of
+ * the classifier sigma(M[v].M[u]) on the positive and negative samples).
+ * When loss_dev is not NULL, every later gosh_train call adds to
+ * loss_dev[j] the running loss of its epoch j: the sum over the epoch's
+ * executed UpdateEmbed calls of -log sigma(x) (positive) or
+ * -log(1 - sigma(x)) (negative), x the dot product the update reads before
+ * it changes the rows; gosh_update_batch adds its batch's sum to loss_dev[0].
+ * Terms are FP32, summed in FP32 within a wave and in FP64 across waves
+ * (atomic adds, so the last bits depend on timing; in deterministic mode
+ * every visit's terms are summed in FP64 in source order).  The caller
+ * zeroes the buffer.  A gosh_train call with more epochs than `capacity`
+ * returns GOSH_E_INVALID_ARG.  loss_dev: device, caller-owned, `capacity`
+ * doubles; NULL (the default) turns recording off.  Recording adds a few
+ * instructions and one atomic per wave to every visit. */
+gosh_status gosh_set_loss_record(gosh_ctx* ctx, double* loss_dev, int64_t capacity);
+
+/* Test hook: when samples_dev is not NULL, gosh_train writes the samples
+ * each visit draws inside the training kernel to samples_dev[src * (1+k) +
+ * t] (t = 0 the positive, -1 for a source without neighbours; t >= 1 the
+ * negatives), overwriting them every epoch (with overlapping epochs, the
+ * entries of one of the launch's epochs remain).  A gosh_train call on a
+ * level with n * (1 + k) > capacity returns GOSH_E_INVALID_ARG.
+ * samples_dev: device, caller-owned int32; NULL (the default) turns it off. */
+gosh_status gosh_set_draw_record(gosh_ctx* ctx, int32_t* samples_dev, int64_t capacity);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* Checks `g` against the graph convention (Section 4.1: the method works on
@@ -203,9 +228,11 @@ gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
  * M[u] += score M[src] with the updated source row.
  * `emb` is a caller-owned device array [n_level, d] of `dt`, updated in
  * place.  Sources of an epoch run concurrently; every row change is applied
- * with atomic adds (FP32: per element; BF16: the exact difference to the
- * rounded value, per 2-element word), so concurrent updates of a shared row
- * are all kept.  BF16 rows are widened to FP32 for
+ * atomically (FP32: atomic adds per element; BF16, per 2-element word: the
+ * packed atomic add of the difference to the rounded value when that
+ * difference is a BF16 value, else a compare-and-swap of the rounded pair),
+ * so concurrent updates of a shared row are all kept and an uncontended
+ * word holds exactly its rounded value.  BF16 rows are widened to FP32 for
  * the arithmetic and every written row is stochastically rounded back
  * (sample rows once per update, the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
  * lr finite and >= 0.  `tag` (24 bits) separates independent random
@@ -463,7 +490,11 @@ gosh_status gosh_draw_samples(gosh_ctx* ctx, const gosh_levels* lv, int32_t leve
  * skip).  Rows are visited concurrently, so the result equals the
  * sequential one only when no row is touched by two listed sources.
  * Stochastic-rounding bits use (level, tag, epoch) and the source id.
- * emb_dev holds n_rows rows; every index must be < n_rows.  Asynchronous. */
+ * emb_dev holds n_rows rows; every index must be < n_rows.  The write
+ * discipline is gosh_train's for a level of n_rows vertices: with
+ * gosh_set_plain_negatives(ctx, m), m > 0 and n_rows >= m (and not in
+ * deterministic mode), negative rows are written with plain stores, so this
+ * call runs the timed kernel's store path on chosen samples.  Asynchronous. */
 gosh_status gosh_update_batch(gosh_ctx* ctx, void* emb_dev, gosh_dtype dt, int32_t d,
                               int64_t n_rows, int32_t nsrc, const int32_t* src_dev,
                               const int32_t* samples_dev, int32_t k, float lr,

@@ -65,6 +65,13 @@ def lib():
         L.orc_train.argtypes = [_i64p, _i32p, C.c_int64, C.POINTER(_Emb), C.c_int32, C.c_double,
                                 C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_int64, C.c_int64]
         L.orc_train.restype = C.c_int64
+        L.orc_train_loss.argtypes = [_i64p, _i32p, C.c_int64, C.POINTER(_Emb), C.c_int32, C.c_double,
+                                     C.c_int32, C.c_uint64, C.c_int32, C.c_uint32,
+                                     np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")]
+        L.orc_train_loss.restype = C.c_int64
+        L.orc_draw_all.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32,
+                                   C.c_int32, _i32p]
+        L.orc_draw_all.restype = None
         L.orc_coarsen_map.argtypes = [_i64p, _i32p, C.c_int64, _i32p, C.c_void_p]
         L.orc_coarsen_map.restype = C.c_int64
         L.orc_coarse_graph.argtypes = [_i64p, _i32p, C.c_int64, _i32p, C.c_int64, _i64p, _i32p]
@@ -128,11 +135,11 @@ def draw_samples(offsets, indices, seed, level, tag, epoch, src, k) -> np.ndarra
 
 def draw_all(offsets, indices, seed, level, tag, epoch, k) -> np.ndarray:
     """[n, 1+k] samples of every source for one epoch."""
+    offsets, indices = _csr(offsets, indices)
     n = len(offsets) - 1
-    out = np.zeros((n, 1 + k), np.int32)
-    for s in range(n):
-        out[s] = draw_samples(offsets, indices, seed, level, tag, epoch, s, k)
-    return out
+    out = np.zeros((max(n, 1), 1 + k), np.int32)
+    lib().orc_draw_all(offsets, indices, n, seed, level, tag, epoch, k, out.reshape(-1))
+    return out[:n]
 
 
 def sr_bits(seed, level, tag, epoch, src, slot, e, d) -> int:
@@ -207,6 +214,22 @@ def train(offsets, indices, M, epochs, lr, k, seed, level=0, tag=0, src_lo=0, sr
                                src_lo, hi))
 
 
+def train_loss(offsets, indices, M, epochs, lr, k, seed, level=0, tag=0):
+    """Sequential Algorithm 3 (as train) over all sources; returns (updates,
+    float64 [epochs] running loss of each epoch: the Section 2 objective
+    summed over the epoch's executed updates, each taken before its update)."""
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    if M.shape[0] != n:
+        raise ValueError("embedding rows != |V|")
+    if not 0 <= k <= 15:
+        raise ValueError("k out of range")
+    e = _emb(M)
+    out = np.zeros(max(epochs, 1), np.float64)
+    u = lib().orc_train_loss(offsets, indices, n, C.byref(e), epochs, lr, k, seed, level, tag, out)
+    return int(u), out[:epochs]
+
+
 # --------------------------------------------------------------------------- coarsening
 def coarsen_map(offsets, indices):
     """(map int32[n], n_next, order int32[n]) of one MultiEdgeCollapse level."""
@@ -267,24 +290,51 @@ def lr_at(lr: float, j: int, e_i: int) -> float:
     return lr * max(1.0 - j / e_i, 1e-4)
 
 
+def unit_epochs(sched, graphs, unit="passes"):
+    """Epochs of each level in Algorithm 3 passes for an epoch unit.
+
+    "passes": one epoch is one pass of Algorithm 3 (every vertex a source
+    once), the schedule as it is.  "edges": the unit of the paper's
+    experiments, one epoch = |E| updates (the note under Table 3): level i
+    has nnz_i / 2 undirected edges and a pass visits n_i sources, so its
+    share e_i becomes e_i * ceil(nnz_i / (2 n_i)) passes (at least one pass
+    per epoch, also for an edgeless level)."""
+    if unit == "passes":
+        return np.asarray(sched, np.int32)
+    if unit != "edges":
+        raise ValueError(f"unknown epoch unit {unit!r}")
+    out = []
+    for e_i, (off, _) in zip(sched, graphs):
+        n_i, nnz_i = len(off) - 1, int(off[-1])
+        mult = max(1, -(-nnz_i // (2 * n_i))) if n_i > 0 else 1
+        out.append(int(e_i) * mult)
+    return np.asarray(out, np.int32)
+
+
 def gosh_embed(offsets, indices, init_fn, d, e, p, lr, k, seed, threshold=100,
-               ratio=0.8, bf16=False, tag=0, levels=None):
+               ratio=0.8, bf16=False, tag=0, levels=None, epoch_unit="passes", losses=None):
     """Algorithm 2: coarsen, initialise the coarsest rows with
     ``init_fn(n_coarsest, d)`` (float32), train levels D-1 .. 0 with their
-    epoch share, expanding each trained level to the next finer one.
-    Returns (M_0, info) with M_0 float64 or BF16 bits."""
+    epoch share (in the given epoch unit, see unit_epochs), expanding each
+    trained level to the next finer one.  Returns (M_0, info) with M_0
+    float64 or BF16 bits.  With a dict `losses`, losses[i] receives level
+    i's per-epoch running loss (train_loss)."""
     if levels is None:
         graphs, maps = coarsen_levels(offsets, indices, threshold, ratio)
     else:
         graphs, maps = levels
     D = len(graphs)
-    sched = epoch_schedule(e, p, D)
+    sched = unit_epochs(epoch_schedule(e, p, D), graphs, epoch_unit)
     init = np.asarray(init_fn(len(graphs[-1][0]) - 1, d), dtype=np.float32)
     M = f32_to_bf16_rne(init).reshape(init.shape) if bf16 else init.astype(np.float64)
     updates = []
     for i in range(D - 1, -1, -1):
         off, idx = graphs[i]
-        updates.append(train(off, idx, M, int(sched[i]), lr, k, seed, level=i, tag=tag))
+        if losses is not None:
+            u, losses[i] = train_loss(off, idx, M, int(sched[i]), lr, k, seed, level=i, tag=tag)
+            updates.append(u)
+        else:
+            updates.append(train(off, idx, M, int(sched[i]), lr, k, seed, level=i, tag=tag))
         if i > 0:
             M = prolong(M, maps[i - 1])
     return M, {"levels": D, "schedule": sched, "sizes": [len(g[0]) - 1 for g in graphs],

@@ -194,10 +194,13 @@ static uint32_t sr_bits_hi(uint64_t seed, int32_t level, uint32_t tag, int32_t e
 }
 
 /* One visit (Algorithm 1 on each sample in turn).  BF16 rounding bits come
- * from the stream (sid, epoch, kind sr_kind, slot, block hi << 8 | ...). */
-static int32_t visit_stream(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
-                            double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
-                            int64_t sid, uint32_t sr_kind, uint32_t hi)
+ * from the stream (sid, epoch, kind sr_kind, slot, block hi << 8 | ...).
+ * loss (may be NULL) accumulates the objective of Section 2 at each executed
+ * update, evaluated on the rows the update reads (before it changes them):
+ * -log sigma(x) for the positive, -log(1 - sigma(x)) for a negative. */
+static int32_t visit_stream_loss(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                                 double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                                 int64_t sid, uint32_t sr_kind, uint32_t hi, double* loss)
 {
     const int32_t d = M->d;
     double* s = (double*)malloc(sizeof(double) * (size_t)d);
@@ -216,6 +219,8 @@ static int32_t visit_stream(orc_emb* M, int64_t src, const int32_t* samples, int
         for (int32_t e = 0; e < d; ++e)
             x += s[e] * m[e];
         const double score = (b - orc_sigmoid(x)) * lr;
+        if (loss)
+            *loss += orc_loss(x, t == 0);
         for (int32_t e = 0; e < d; ++e)
             s[e] += m[e] * score;
         for (int32_t e = 0; e < d; ++e) {
@@ -240,6 +245,13 @@ static int32_t visit_stream(orc_emb* M, int64_t src, const int32_t* samples, int
     free(s);
     free(m);
     return done;
+}
+
+static int32_t visit_stream(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
+                            double lr, uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
+                            int64_t sid, uint32_t sr_kind, uint32_t hi)
+{
+    return visit_stream_loss(M, src, samples, k, lr, seed, level, tag, epoch, sid, sr_kind, hi, NULL);
 }
 
 static int32_t visit_hi(orc_emb* M, int64_t src, const int32_t* samples, int32_t k,
@@ -284,6 +296,37 @@ int64_t orc_train(const int64_t* offsets, const int32_t* indices, int64_t n,
         }
     }
     return done;
+}
+
+/* Algorithm 3 run sequentially as orc_train, with loss_out[j] (epochs
+ * entries) receiving the sum over epoch j's executed updates of the
+ * objective of Section 2 at the moment of each update (the running loss). */
+int64_t orc_train_loss(const int64_t* offsets, const int32_t* indices, int64_t n,
+                       orc_emb* M, int32_t epochs, double lr, int32_t k,
+                       uint64_t seed, int32_t level, uint32_t tag, double* loss_out)
+{
+    int32_t samples[64];
+    int64_t done = 0;
+    for (int32_t j = 0; j < epochs; ++j) {
+        double f = 1.0 - (double)j / (double)epochs;
+        double lrj = lr * (f > 1e-4 ? f : 1e-4);
+        double acc = 0.0;
+        for (int64_t src = 0; src < n; ++src) {
+            orc_draw_samples(offsets, indices, n, seed, level, tag, j, src, k, samples);
+            done += visit_stream_loss(M, src, samples, k, lrj, seed, level, tag, j, src, 1u, 0u, &acc);
+        }
+        loss_out[j] = acc;
+    }
+    return done;
+}
+
+/* Samples of every source of one epoch (orc_draw_samples for src = 0..n-1):
+ * out[src * (1 + k) + t]. */
+void orc_draw_all(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,
+                  int32_t level, uint32_t tag, int32_t epoch, int32_t k, int32_t* out)
+{
+    for (int64_t src = 0; src < n; ++src)
+        orc_draw_samples(offsets, indices, n, seed, level, tag, epoch, src, k, out + src * (1 + k));
 }
 
 /* ------------------------------------------------------------------------ */

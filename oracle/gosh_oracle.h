@@ -86,6 +86,16 @@ int64_t orc_train(const int64_t* offsets, const int32_t* indices, int64_t n,
                   uint64_t seed, int32_t level, uint32_t tag,
                   int64_t src_lo, int64_t src_hi);
 
+/* orc_train over all sources with loss_out[j] = sum over epoch j's executed
+ * updates of the Section 2 objective at each update (running loss, FP64). */
+int64_t orc_train_loss(const int64_t* offsets, const int32_t* indices, int64_t n,
+                       orc_emb* M, int32_t epochs, double lr, int32_t k,
+                       uint64_t seed, int32_t level, uint32_t tag, double* loss_out);
+
+/* orc_draw_samples for every source of one epoch: out[src * (1 + k) + t]. */
+void orc_draw_all(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,
+                  int32_t level, uint32_t tag, int32_t epoch, int32_t k, int32_t* out);
+
 /* One level of Algorithm 4 (MultiEdgeCollapse): fills map[n] and the
  * processing order order[n] (may be NULL); returns |V_{i+1}|. */
 int64_t orc_coarsen_map(const int64_t* offsets, const int32_t* indices, int64_t n,

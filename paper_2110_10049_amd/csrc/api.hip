@@ -255,6 +255,20 @@ gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices) {
     return GOSH_OK;
 }
 
+gosh_status gosh_set_draw_record(gosh_ctx* ctx, int32_t* samples_dev, int64_t capacity) {
+    if (!ctx || capacity < 0 || (samples_dev && capacity == 0)) return GOSH_E_INVALID_ARG;
+    ctx->c.record = samples_dev;
+    ctx->c.record_cap = samples_dev ? capacity : 0;
+    return GOSH_OK;
+}
+
+gosh_status gosh_set_loss_record(gosh_ctx* ctx, double* loss_dev, int64_t capacity) {
+    if (!ctx || capacity < 0 || (loss_dev && capacity == 0)) return GOSH_E_INVALID_ARG;
+    ctx->c.loss = loss_dev;
+    ctx->c.loss_cap = loss_dev ? capacity : 0;
+    return GOSH_OK;
+}
+
 gosh_status gosh_validate_csr(gosh_ctx* ctx, const gosh_csr* g, int check_symmetry) {
     if (!ctx) return GOSH_E_INVALID_ARG;
     return guarded(ctx, [&] {

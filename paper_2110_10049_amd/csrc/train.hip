@@ -44,11 +44,15 @@ __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane % L;
     if constexpr (MODE == kSequential) {
-        // one wave, sources strictly in ascending id order
+        // one wave, sources strictly in ascending id order; the running loss
+        // is summed per visit in FP64
+        double acc = 0.0;
         for (int64_t s = 0; s < P.n; ++s) {
-            visit<BF16, D, KMAX, Off, MODE>(P, s, grp == 0, gl);
+            acc += visit<BF16, D, KMAX, Off, MODE>(P, s, grp == 0, gl);
             __threadfence();
         }
+        if (P.loss && lane == 0 && acc != 0.0)
+            __hip_atomic_fetch_add(P.loss, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
         const int64_t slot = wave * G + grp;
@@ -60,12 +64,16 @@ __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
                 Q.epoch = P.epoch + static_cast<uint32_t>(ep);
                 const double f = 1.0 - static_cast<double>(Q.epoch) / static_cast<double>(P.e_total);
                 Q.lr = static_cast<float>(static_cast<double>(P.lr0) * (f > 1e-4 ? f : 1e-4));
-                visit<BF16, D, KMAX, Off, MODE>(Q, slot - ep * P.n, slot < P.n * P.span, gl);
+                const float l = visit<BF16, D, KMAX, Off, MODE>(Q, slot - ep * P.n, slot < P.n * P.span, gl);
+                if (P.loss && gl == 0 && l != 0.0f)
+                    __hip_atomic_fetch_add(P.loss + ep, static_cast<double>(l), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 return;
             }
         }
         const int64_t limit = (MODE == kExplicit) ? P.nsrc : P.n;
-        visit<BF16, D, KMAX, Off, MODE>(P, slot, slot < limit, gl);
+        const float l = visit<BF16, D, KMAX, Off, MODE>(P, slot, slot < limit, gl);
+        if (P.loss) wave_add_loss<L>(P.loss, l, gl);
     }
 }
 
@@ -220,11 +228,19 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     P.e_total = epochs;
     P.lr0 = lr;
     P.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && L.n >= c->plain_neg_min) ? 1 : 0;
+    if (c->record) {
+        GOSH_REQUIRE(c->record_cap >= L.n * (1 + k), GOSH_E_INVALID_ARG,
+                     "draw record buffer holds fewer than n * (1 + k) entries");
+        P.record = c->record;
+    }
+    GOSH_REQUIRE(!c->loss || c->loss_cap >= epochs, GOSH_E_INVALID_ARG,
+                 "loss record buffer holds fewer entries than the call's epochs");
     for (int j = 0; j < epochs; j += span) {
         const double f = 1.0 - static_cast<double>(j) / static_cast<double>(epochs);
         P.lr = static_cast<float>(static_cast<double>(lr) * (f > 1e-4 ? f : 1e-4));
         P.epoch = static_cast<uint32_t>(j);
         P.span = std::min(span, epochs - j);
+        P.loss = c->loss ? c->loss + j : nullptr;
         fn(P, L.n * P.span, c->stream);
         GOSH_HIP(hipGetLastError());
     }
@@ -258,6 +274,8 @@ void update_batch(Ctx* c, void* emb, gosh_dtype dt, int d, int64_t n_rows, int n
     P.src_list = src;
     P.samples = samples;
     P.nsrc = nsrc;
+    P.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && n_rows >= c->plain_neg_min) ? 1 : 0;
+    P.loss = c->loss;   // the batch's running loss goes to entry 0
     Launcher fn = pick<kExplicit>(dt, d, k, false);
     fn(P, nsrc, c->stream);
     GOSH_HIP(hipGetLastError());

@@ -38,6 +38,8 @@ struct TrainParams {
     int32_t e_total;
     float lr0;
     int32_t plain_neg;        // negatives written with plain stores instead of atomic adds
+    int32_t* record;          // optional: samples drawn by each visit, [n][1+k]
+    double* loss;             // optional: running loss per epoch of the launch (index = epoch - first)
 };
 
 enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
@@ -70,14 +72,23 @@ struct Lanes {
 // a plain read-modify-write store would drop every concurrent update but the
 // last one -- on small levels, where a whole epoch is in flight at once,
 // nearly all of them.  FP32 rows receive their changes with atomic adds.
-// BF16 rows receive, per 32-bit word, the exact difference between the
-// stochastically rounded new value and the value this visit started from,
-// through the packed BF16 atomic add: uncontended, the stored row becomes
-// exactly the rounded value (the difference of two nearby BF16 values is
-// itself a BF16 value); contended, the concurrent changes add up in value
-// space.  (Adding bit-pattern differences with integer atomics would be
-// faster but wraps through the sign when many concurrent updates move one
-// element across zero.)  The L2 atomic units bound the training kernel.
+// BF16 rows: per 32-bit word (two elements), the change from the pair this
+// visit started from (cur) to the stochastically rounded new pair (out).
+// When both differences out - cur are BF16 values (so cur + diff is exactly
+// out), the word takes the packed BF16 atomic add of the differences:
+// uncontended it becomes exactly out, contended the concurrent changes add
+// up in value space.  Otherwise (a difference needs more than 8 significant
+// bits: a sign crossing, or a change much larger or much smaller than the
+// element) one packed add would round the difference and then the sum, so
+// that half takes two adds through zero instead, -cur then +out, each exact
+// (x - x = 0 and 0 + out = out); a concurrent add landing between them still
+// adds up, and a concurrent reader may meanwhile see 0, which lies within
+// |out - cur| of both ends for these halves.  Uncontended, every word of a
+// committed row therefore holds exactly the stochastically rounded result,
+// and no commit waits for a returned value.  (Adding
+// bit-pattern differences with integer atomics would be faster but wraps
+// through the sign when many concurrent updates move one element across
+// zero.)  The L2 atomic units bound the training kernel.
 template <bool BF16>
 struct RowIO;
 
@@ -121,33 +132,38 @@ __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
+__device__ __forceinline__ void atomic_add_bf16x2(uint32_t* p, uint32_t d) {
+    __builtin_amdgcn_global_atomic_fadd_v2bf16((__attribute__((address_space(1))) bf16x2_t*)p,
+                                               __builtin_bit_cast(bf16x2_t, d));
+}
+
+// BF16 rows are held in registers as their 32-bit words (two elements each,
+// low half the even element) and widened to FP32 where the arithmetic reads
+// them, which halves the registers a visit's 1+k sample rows take.
 template <>
 struct RowIO<true> {
     using Elem = uint16_t;
     template <int D, bool COH>
-    __device__ static void load(const uint16_t* M, int64_t row, int gl, float (&x)[Lanes<true, D>::kEPL]) {
+    __device__ static void load(const uint16_t* M, int64_t row, int gl, uint32_t (&w)[Lanes<true, D>::kWPL]) {
         constexpr int L = Lanes<true, D>::kL;
         const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * D) + gl;
 #pragma unroll
         for (int i = 0; i < Lanes<true, D>::kWPL; ++i) {
-            uint32_t w;
             if constexpr (COH)
-                w = __hip_atomic_load(p + L * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                w[i] = __hip_atomic_load(p + L * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else
-                w = p[L * i];
-            x[2 * i] = bf16_lo(w);
-            x[2 * i + 1] = bf16_hi(w);
+                w[i] = p[L * i];
         }
     }
-    // cur: the values this visit last saw (exact BF16), v: the FP32 results,
-    // r: the lane's Philox block (block gl mod d/8 of the row).  Word w of the
-    // row takes 32-bit output word w div (d/8) of its block (low half for the
-    // even element).  out: the rounded values.
-    // PLAIN: store the rounded words instead of adding the difference.
+    // cur: the words this visit last saw, v: the FP32 results, r: the lane's
+    // Philox block (block gl mod d/8 of the row).  Word w of the row takes
+    // 32-bit output word w div (d/8) of its block (low half for the even
+    // element).  out: the rounded words.
+    // PLAIN: store the rounded words instead of committing the change.
     template <int D, bool PLAIN = false>
-    __device__ static void commit(uint16_t* M, int64_t row, int gl, const float (&cur)[Lanes<true, D>::kEPL],
+    __device__ static void commit(uint16_t* M, int64_t row, int gl, const uint32_t (&cur)[Lanes<true, D>::kWPL],
                                   const float (&v)[Lanes<true, D>::kEPL], uint4 r,
-                                  float (&out)[Lanes<true, D>::kEPL]) {
+                                  uint32_t (&out)[Lanes<true, D>::kWPL]) {
         using Ly = Lanes<true, D>;
         constexpr int L = Ly::kL;
         uint32_t* p = reinterpret_cast<uint32_t*>(M + row * D) + gl;
@@ -160,17 +176,25 @@ struct RowIO<true> {
             const uint32_t bits = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
             const uint32_t t0 = bf16_sr(v[2 * i], bits & 0xFFFFu);
             const uint32_t t1 = bf16_sr(v[2 * i + 1], bits >> 16);
-            out[2 * i] = __uint_as_float(t0 << 16);
-            out[2 * i + 1] = __uint_as_float(t1 << 16);
+            const uint32_t want = (t0 & 0xFFFFu) | (t1 << 16);
+            out[i] = want;
             if constexpr (PLAIN) {
-                p[L * i] = (t0 & 0xFFFFu) | (t1 << 16);
+                p[L * i] = want;
             } else {
-                const uint32_t d = bf16_rne_bits(out[2 * i] - cur[2 * i]) |
-                                   (bf16_rne_bits(out[2 * i + 1] - cur[2 * i + 1]) << 16);
-                if (d != 0u)
-                    __builtin_amdgcn_global_atomic_fadd_v2bf16(
-                        (__attribute__((address_space(1))) bf16x2_t*)(p + L * i),
-                        __builtin_bit_cast(bf16x2_t, d));
+                // per half: the exact rounded difference in one add, or,
+                // when out - cur is not a BF16 value, two exact adds through
+                // zero (-cur, then +out)
+                const float c0 = bf16_lo(cur[i]), c1 = bf16_hi(cur[i]);
+                const float o0 = bf16_lo(want), o1 = bf16_hi(want);
+                const uint32_t h0 = bf16_rne_bits(o0 - c0) & 0xFFFFu;
+                const uint32_t h1 = bf16_rne_bits(o1 - c1) & 0xFFFFu;
+                const bool x0 = c0 + bf16_lo(h0) == o0;
+                const bool x1 = c1 + bf16_lo(h1) == o1;
+                const uint32_t a = (x0 ? h0 : (cur[i] & 0xFFFFu) ^ 0x8000u) |
+                                   ((x1 ? h1 : (cur[i] >> 16) ^ 0x8000u) << 16);
+                const uint32_t b2 = (x0 ? 0u : want & 0xFFFFu) | (x1 ? 0u : want & 0xFFFF0000u);
+                if ((a & 0x7FFF7FFFu) != 0u) atomic_add_bf16x2(p + L * i, a);
+                if ((b2 & 0x7FFF7FFFu) != 0u) atomic_add_bf16x2(p + L * i, b2);
             }
         }
     }
@@ -178,6 +202,13 @@ struct RowIO<true> {
 
 __device__ __forceinline__ float sigmoidf_(float x) {
     return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+}
+
+// softplus(z) = log(1 + e^z) in FP32: the logistic loss of Section 2 is
+// softplus(-x) for a positive (-log sigma(x)) and softplus(x) for a negative
+// (-log(1 - sigma(x))).
+__device__ __forceinline__ float softplusf_(float z) {
+    return fmaxf(z, 0.0f) + __logf(1.0f + __expf(-fabsf(z)));
 }
 
 // UpdateEmbed (Algorithm 1) on samples u[0..k] of one source, u[0] the
@@ -188,71 +219,136 @@ __device__ __forceinline__ float sigmoidf_(float x) {
 // which the callers precount.  BF16 rounding bits come from the stream (sid,
 // epoch, w2, kind sr_kind | slot t or 255 | block blk_hi << 8 | gl mod d/8).
 // COH: loads bypass the non-coherent caches (rows written by other waves of
-// the same launch).
+// the same launch).  Returns, when want_loss, the visit's running loss: the
+// Section 2 objective of each executed update at the dot it reads (the same
+// value on every lane of the group); 0 otherwise.
 template <bool BF16, int D, int KMAX, bool COH>
-__device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int64_t src,
-                                             typename RowIO<BF16>::Elem* Mo, int64_t self,
-                                             const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
-                                             uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
-                                             uint32_t key0, uint32_t key1, unsigned long long* updates, int gl,
-                                             bool plain_neg = false) {
+__device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, int64_t src,
+                                              typename RowIO<BF16>::Elem* Mo, int64_t self,
+                                              const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
+                                              uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
+                                              uint32_t key0, uint32_t key1, unsigned long long* updates, int gl,
+                                              bool plain_neg = false, bool want_loss = false) {
     using Ly = Lanes<BF16, D>;
     constexpr int L = Ly::kL;
     constexpr int E = Ly::kEPL;
+    constexpr int W = Ly::kWPL;
     using IO = RowIO<BF16>;
     const uint32_t blk = (blk_hi << 8) | static_cast<uint32_t>(gl % Ly::kBlocks);
-    float s[E];
-    float m[KMAX + 1][E];
-    IO::template load<D, COH>(Ms, src, gl, s);
-#pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (t <= k && u[t] >= 0 && u[t] != self) {
-            IO::template load<D, COH>(Mo, u[t], gl, m[t]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) m[t][e] = 0.0f;
-        }
-    }
-
     int done = 0;
-    float s0[E];
+    float lsum = 0.0f;
+    if constexpr (BF16) {
+        // rows as packed BF16 words; element 2i is the low half of word i
+        uint32_t sw[W];
+        uint32_t mw[KMAX + 1][W];
+        IO::template load<D, COH>(Ms, src, gl, sw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) s0[e] = s[e];
+        for (int t = 0; t <= KMAX; ++t) {
+            if (t <= k && u[t] >= 0 && u[t] != self) {
+                IO::template load<D, COH>(Mo, u[t], gl, mw[t]);
+            } else {
 #pragma unroll
-    for (int t = 0; t <= KMAX; ++t) {
-        if (t > k) break;
-        const int32_t ut = u[t];
-        if (ut < 0 || ut == self) {
-            if (t > 0 && ut >= 0 && ut == self && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
-            continue;
-        }
-        // a row sampled earlier in this visit continues from its updated value
-#pragma unroll
-        for (int tp = 0; tp < t; ++tp) {
-            if (u[tp] == ut) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) m[t][e] = m[tp][e];
+                for (int i = 0; i < W; ++i) mw[t][i] = 0u;
             }
         }
-        float x = 0.0f;
+        float s[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) x = fmaf(s[e], m[t][e], x);
-        x = group_sum<L>(x);
-        const float b = (t == 0) ? 1.0f : 0.0f;
-        const float g = (b - sigmoidf_(x)) * lr;
+        for (int i = 0; i < W; ++i) {
+            s[2 * i] = bf16_lo(sw[i]);
+            s[2 * i + 1] = bf16_hi(sw[i]);
+        }
 #pragma unroll
-        for (int e = 0; e < E; ++e) s[e] = fmaf(g, m[t][e], s[e]);
-        if constexpr (BF16) {
+        for (int t = 0; t <= KMAX; ++t) {
+            if (t > k) break;
+            const int32_t ut = u[t];
+            if (ut < 0 || ut == self) {
+                if (t > 0 && ut >= 0 && ut == self && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
+                continue;
+            }
+            // a row sampled earlier in this visit continues from its updated value
+#pragma unroll
+            for (int tp = 0; tp < t; ++tp) {
+                if (u[tp] == ut) {
+#pragma unroll
+                    for (int i = 0; i < W; ++i) mw[t][i] = mw[tp][i];
+                }
+            }
+            float x = 0.0f;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                x = fmaf(s[2 * i], bf16_lo(mw[t][i]), x);
+                x = fmaf(s[2 * i + 1], bf16_hi(mw[t][i]), x);
+            }
+            x = group_sum<L>(x);
+            const float b = (t == 0) ? 1.0f : 0.0f;
+            const float g = (b - sigmoidf_(x)) * lr;
+            if (want_loss) lsum += softplusf_(t == 0 ? -x : x);
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                s[2 * i] = fmaf(g, bf16_lo(mw[t][i]), s[2 * i]);
+                s[2 * i + 1] = fmaf(g, bf16_hi(mw[t][i]), s[2 * i + 1]);
+            }
             const uint4 bits = philox10(
                 make_uint4(sid, epoch, w2, stream_word3(sr_kind, static_cast<uint32_t>(t), blk)), key0, key1);
-            float v[E], out[E];
+            float v[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = fmaf(g, s[e], m[t][e]);
-            if (t > 0 && plain_neg) IO::template commit<D, true>(Mo, ut, gl, m[t], v, bits, out);
-            else IO::template commit<D>(Mo, ut, gl, m[t], v, bits, out);
+            for (int i = 0; i < W; ++i) {
+                v[2 * i] = fmaf(g, s[2 * i], bf16_lo(mw[t][i]));
+                v[2 * i + 1] = fmaf(g, s[2 * i + 1], bf16_hi(mw[t][i]));
+            }
+            uint32_t out[W];
+            if (t > 0 && plain_neg) IO::template commit<D, true>(Mo, ut, gl, mw[t], v, bits, out);
+            else IO::template commit<D>(Mo, ut, gl, mw[t], v, bits, out);
 #pragma unroll
-            for (int e = 0; e < E; ++e) m[t][e] = out[e];
-        } else {
+            for (int i = 0; i < W; ++i) mw[t][i] = out[i];
+            ++done;
+        }
+        if (done) {
+            const uint4 bits = philox10(make_uint4(sid, epoch, w2, stream_word3(sr_kind, 0xFFu, blk)), key0, key1);
+            uint32_t out[W];
+            IO::template commit<D>(Ms, src, gl, sw, s, bits, out);
+        }
+    } else {
+        float s[E];
+        float m[KMAX + 1][E];
+        IO::template load<D, COH>(Ms, src, gl, s);
+#pragma unroll
+        for (int t = 0; t <= KMAX; ++t) {
+            if (t <= k && u[t] >= 0 && u[t] != self) {
+                IO::template load<D, COH>(Mo, u[t], gl, m[t]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) m[t][e] = 0.0f;
+            }
+        }
+        float s0[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) s0[e] = s[e];
+#pragma unroll
+        for (int t = 0; t <= KMAX; ++t) {
+            if (t > k) break;
+            const int32_t ut = u[t];
+            if (ut < 0 || ut == self) {
+                if (t > 0 && ut >= 0 && ut == self && updates && gl == 0) atomicAdd(updates, ~0ull);  // -1
+                continue;
+            }
+            // a row sampled earlier in this visit continues from its updated value
+#pragma unroll
+            for (int tp = 0; tp < t; ++tp) {
+                if (u[tp] == ut) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) m[t][e] = m[tp][e];
+                }
+            }
+            float x = 0.0f;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x = fmaf(s[e], m[t][e], x);
+            x = group_sum<L>(x);
+            const float b = (t == 0) ? 1.0f : 0.0f;
+            const float g = (b - sigmoidf_(x)) * lr;
+            if (want_loss) lsum += softplusf_(t == 0 ? -x : x);
+#pragma unroll
+            for (int e = 0; e < E; ++e) s[e] = fmaf(g, m[t][e], s[e]);
             float dx[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -261,26 +357,24 @@ __device__ __forceinline__ void update_chain(typename RowIO<BF16>::Elem* Ms, int
             }
             if (t > 0 && plain_neg) IO::template store<D>(Mo, ut, gl, m[t]);
             else IO::template add<D>(Mo, ut, gl, dx);
+            ++done;
         }
-        ++done;
-    }
-    if (done) {
-        if constexpr (BF16) {
-            const uint4 bits = philox10(make_uint4(sid, epoch, w2, stream_word3(sr_kind, 0xFFu, blk)), key0, key1);
-            float out[E];
-            IO::template commit<D>(Ms, src, gl, s0, s, bits, out);
-        } else {
+        if (done) {
             float dx[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) dx[e] = s[e] - s0[e];
             IO::template add<D>(Ms, src, gl, dx);
         }
     }
+    return lsum;
 }
 
 // One source visit: draws (or reads) the samples and applies the updates.
+// Returns the visit's running loss when P.loss is set (see update_chain), 0
+// for an inactive slot.  With P.record set, the drawn samples are written to
+// record[src * (1 + k) + t].
 template <bool BF16, int D, int KMAX, class Off, int MODE>
-__device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool active, int gl) {
+__device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool active, int gl) {
     using Elem = typename RowIO<BF16>::Elem;
     Elem* M = static_cast<Elem*>(P.emb);
     const int k = P.k;
@@ -330,12 +424,29 @@ __device__ __forceinline__ void visit(const TrainParams& P, int64_t slot, bool a
                 const int32_t pos = P.indices[beg + scale_u32(wd[0], deg)];
                 u[0] = (pos >= 0 && pos < P.n) ? pos : -1;
             }
+            if (P.record && gl == 0) {
+#pragma unroll
+                for (int t = 0; t <= KMAX; ++t)
+                    if (t <= k) P.record[src * (1 + k) + t] = u[t];
+            }
         }
     }
-    if (!active) return;
-    update_chain<BF16, D, KMAX, MODE == kPersistent>(M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src),
-                                                     P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates, gl,
-                                                     MODE == kEpoch && P.plain_neg != 0);
+    if (!active) return 0.0f;
+    return update_chain<BF16, D, KMAX, MODE == kPersistent>(
+        M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates,
+        gl, (MODE == kEpoch || MODE == kExplicit) && P.plain_neg != 0, P.loss != nullptr);
+}
+
+// Adds the running losses of the wave's groups (`l` on every lane of a
+// group, L lanes per group) to *dst: an FP32 sum over the wave, one FP64
+// atomic add per wave.
+template <int L>
+__device__ __forceinline__ void wave_add_loss(double* dst, float l, int gl) {
+    float v = (gl == 0) ? l : 0.0f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v != 0.0f)
+        __hip_atomic_fetch_add(dst, static_cast<double>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace train_detail

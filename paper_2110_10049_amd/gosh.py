@@ -84,6 +84,8 @@ _SIGNATURES = [
     ("gosh_set_deterministic", C.c_int, [_P, C.c_int]),
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
+    ("gosh_set_loss_record", C.c_int, [_P, _P, C.c_int64]),
+    ("gosh_set_draw_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_trim", C.c_int, [_P]),
     ("gosh_set_coarsen_mode", C.c_int, [_P, C.c_int, C.c_int64]),
     ("gosh_validate_csr", C.c_int, [_P, C.POINTER(gosh_csr), C.c_int]),
@@ -217,6 +219,25 @@ class Context:
     def set_plain_negatives(self, min_vertices: int):
         """Plain stores for negative rows on levels of at least min_vertices vertices (0 = off)."""
         self.check(self._L.gosh_set_plain_negatives(self.h, min_vertices))
+
+    def set_loss_record(self, loss: "torch.Tensor | None"):
+        """Running loss per epoch of later gosh_train calls, added to a float64
+        device tensor (the caller zeroes it); None turns recording off."""
+        if loss is None:
+            self.check(self._L.gosh_set_loss_record(self.h, None, 0))
+        else:
+            self.check(self._L.gosh_set_loss_record(self.h, _dev(loss, torch.float64, "loss"), loss.numel()))
+        self._loss_buf = loss   # keep alive while recording
+
+    def set_draw_record(self, samples: "torch.Tensor | None"):
+        """Samples drawn inside gosh_train, written to an int32 device tensor
+        [n, 1+k] (test hook); None turns it off."""
+        if samples is None:
+            self.check(self._L.gosh_set_draw_record(self.h, None, 0))
+        else:
+            self.check(self._L.gosh_set_draw_record(self.h, _dev(samples, torch.int32, "samples"),
+                                                    samples.numel()))
+        self._draw_buf = samples
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
