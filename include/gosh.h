@@ -317,8 +317,13 @@ typedef enum {
  * first time a (dtype, d, k, size class) is seen and caches the winner (also
  * appended to the file named by the GOSH_TUNE_CACHE environment variable).
  * chosen_out (may be NULL) receives {mode, blocks per CU, chunk length} of
- * the execution used.  Synchronous.  Errors as gosh_train; a scheduling
- * failure inside the persistent launch returns GOSH_E_DEVICE. */
+ * the execution used.  In deterministic mode (gosh_set_deterministic) the
+ * persistent launch is used with each job epoch as one task whose sources
+ * are visited one at a time in ascending id order: every job then gets
+ * exactly the result of gosh_train in deterministic mode (sequential
+ * Algorithm 3), independent of timing; chosen_out reports chunk length 0.
+ * Synchronous.  Errors as gosh_train; a scheduling failure inside the
+ * persistent launch returns GOSH_E_DEVICE. */
 gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs,
                                gosh_dtype dt, int32_t d, int32_t k, gosh_batch_mode mode,
                                uint64_t* updates_dev, int32_t* chosen_out);

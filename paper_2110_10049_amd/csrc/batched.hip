@@ -66,6 +66,7 @@ struct PersistArgs {
     unsigned long long* updates;     // self-negative decrements (may be null)
     unsigned int* error;
     unsigned long long spin_limit;
+    int32_t seq;                     // deterministic: a task is a whole job epoch, visited in source order
 };
 
 struct MultiArgs {
@@ -162,9 +163,18 @@ __global__ __launch_bounds__(kBlock) void k_persist(PersistArgs A) {
             const TrainParams P = job_params(J, e, A.k, A.key0, A.key1, A.updates);
             const int64_t beg = c * A.chunk;
             const int64_t end = min(J.n, beg + A.chunk);
-            for (int64_t base = beg; base < end; base += G) {
-                const int64_t src = base + grp;
-                visit_job<BF16, D, KMAX, kPersistent>(J, P, src, src < end, gl);
+            if (A.seq) {
+                // one source at a time in ascending id order (Algorithm 3's
+                // loop run sequentially, as gosh_train's deterministic mode)
+                for (int64_t src = beg; src < end; ++src) {
+                    visit_job<BF16, D, KMAX, kPersistent>(J, P, src, grp == 0, gl);
+                    __threadfence();
+                }
+            } else {
+                for (int64_t base = beg; base < end; base += G) {
+                    const int64_t src = base + grp;
+                    visit_job<BF16, D, KMAX, kPersistent>(J, P, src, src < end, gl);
+                }
             }
         }
         // the wave's updates are performed before the task counts as done
@@ -186,6 +196,14 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiArgs A) {
     const BJob J = A.jobs[j];
     const TrainParams P = job_params(J, A.epoch, A.k, A.key0, A.key1, A.updates);
     visit_job<BF16, D, KMAX, kEpoch>(J, P, slot - A.job_src0[j], true, gl);
+}
+
+// Clears `n` 64-bit words (a kernel rather than a memset node, so that the
+// call stays valid inside a captured stream).
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0ull;
 }
 
 // Base count of UpdateEmbed calls of each job (self-negatives are
@@ -290,8 +308,75 @@ void build_plan(Ctx* c, const gosh_job* in, int njobs, Plan& P) {
 struct RunShape {
     int mode;            // GOSH_BATCH_PERSISTENT or GOSH_BATCH_EPOCH_GRAPH
     int blocks_per_cu;
-    int chunk_iters;
+    int chunk_iters;     // sources per task = chunk_iters * sources per wave (0: a whole job, visited in order)
 };
+
+// Device tables of one persistent launch (see PersistArgs).
+struct PersistTables {
+    BJob* jobs;                      // [njobs]
+    int64_t* round_start;            // [max_e + 1]
+    int64_t* task0;                  // [njobs + 1]
+    int32_t* active;                 // [max_e]
+    unsigned long long* ctr;         // [njobs + 1]: done counters, then the task counter
+    unsigned int* error;             // one word (cleared by the caller)
+};
+
+// Host side of the persistent execution: tasks per job and epoch round, the
+// tables copied into `T`, counters cleared, one launch.  `jobs` holds the
+// jobs sorted by epochs (descending) with epochs already capped.
+void launch_persistent(Ctx* c, std::vector<BJob>& jobs, const std::vector<int32_t>& active, const RunShape& R,
+                       const Kernels& K, int k, unsigned long long* updates, const PersistTables& T) {
+    const int njobs = static_cast<int>(jobs.size());
+    const int max_e = static_cast<int>(active.size());
+    const bool seq = R.chunk_iters == 0;
+    int64_t chunk = static_cast<int64_t>(K.per_wave) * R.chunk_iters;
+    if (seq) {
+        chunk = 1;
+        for (const auto& J : jobs) chunk = std::max<int64_t>(chunk, J.n);
+    }
+    std::vector<int64_t> task0(njobs + 1, 0);
+    for (int i = 0; i < njobs; ++i) {
+        jobs[i].nchunks = ceil_div(jobs[i].n, chunk);
+        task0[i + 1] = task0[i] + jobs[i].nchunks;
+    }
+    std::vector<int64_t> round_start(max_e + 1, 0);
+    for (int e = 0; e < max_e; ++e) round_start[e + 1] = round_start[e] + task0[active[e]];
+    GOSH_HIP(hipMemcpyAsync(T.jobs, jobs.data(), sizeof(BJob) * njobs, hipMemcpyHostToDevice, c->stream));
+    GOSH_HIP(hipMemcpyAsync(T.round_start, round_start.data(), sizeof(int64_t) * (max_e + 1), hipMemcpyHostToDevice,
+                            c->stream));
+    GOSH_HIP(hipMemcpyAsync(T.task0, task0.data(), sizeof(int64_t) * (njobs + 1), hipMemcpyHostToDevice, c->stream));
+    GOSH_HIP(hipMemcpyAsync(T.active, active.data(), sizeof(int32_t) * max_e, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_zero_u64, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(njobs + 1, 256), 64))),
+                       dim3(256), 0, c->stream, T.ctr, static_cast<int64_t>(njobs + 1));
+    GOSH_HIP(hipGetLastError());
+    PersistArgs A{};
+    A.jobs = T.jobs;
+    A.njobs = njobs;
+    A.k = k;
+    A.key0 = static_cast<uint32_t>(c->seed);
+    A.key1 = static_cast<uint32_t>(c->seed >> 32);
+    A.chunk = chunk;
+    A.round_start = T.round_start;
+    A.round_jobs = T.active;
+    A.job_task0 = T.task0;
+    A.max_e = max_e;
+    A.next_task = T.ctr + njobs;
+    A.done = T.ctr;
+    A.updates = updates;
+    A.error = T.error;
+    A.spin_limit = 1ull << 22;   // a few seconds of polling
+    A.seq = seq ? 1 : 0;
+    int cus = 0;
+    GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    // no more waves than tasks in the first (largest) epoch round: extra
+    // waves could only poll the done counters of epochs not yet reached
+    const int64_t round0 = round_start[1] - round_start[0];
+    const int64_t waves =
+        std::min<int64_t>(static_cast<int64_t>(cus) * std::max(R.blocks_per_cu, 1) * (kBlock / 64), round0);
+    const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, ceil_div(waves, kBlock / 64)));
+    void* args[] = {&A};
+    GOSH_HIP(hipLaunchKernel(K.persist, dim3(blocks), dim3(kBlock), args, 0, c->stream));
+}
 
 // Runs the plan's jobs (with their epochs capped at `epochs_cap` if > 0).
 void run(Ctx* c, Plan& P, const RunShape& R, const Kernels& K, int d, int k, int epochs_cap,
@@ -310,49 +395,13 @@ void run(Ctx* c, Plan& P, const RunShape& R, const Kernels& K, int d, int k, int
     }
     const uint32_t key0 = static_cast<uint32_t>(c->seed), key1 = static_cast<uint32_t>(c->seed >> 32);
     if (R.mode == GOSH_BATCH_PERSISTENT) {
-        const int64_t chunk = static_cast<int64_t>(K.per_wave) * R.chunk_iters;
-        std::vector<int64_t> task0(njobs + 1, 0);
-        for (int i = 0; i < njobs; ++i) {
-            jobs[i].nchunks = ceil_div(jobs[i].n, chunk);
-            task0[i + 1] = task0[i] + jobs[i].nchunks;
-        }
-        std::vector<int64_t> round_start(max_e + 1, 0);
-        for (int e = 0; e < max_e; ++e) round_start[e + 1] = round_start[e] + task0[active[e]];
         DevBuf<BJob> dj(c, njobs);
         DevBuf<int64_t> drs(c, max_e + 1), dt0(c, njobs + 1);
         DevBuf<int32_t> dact(c, max_e);
         DevBuf<unsigned long long> ctr(c, njobs + 1);
-        GOSH_HIP(hipMemcpyAsync(dj.p, jobs.data(), sizeof(BJob) * njobs, hipMemcpyHostToDevice, c->stream));
-        GOSH_HIP(hipMemcpyAsync(drs.p, round_start.data(), sizeof(int64_t) * (max_e + 1), hipMemcpyHostToDevice,
-                                c->stream));
-        GOSH_HIP(hipMemcpyAsync(dt0.p, task0.data(), sizeof(int64_t) * (njobs + 1), hipMemcpyHostToDevice, c->stream));
-        GOSH_HIP(hipMemcpyAsync(dact.p, active.data(), sizeof(int32_t) * max_e, hipMemcpyHostToDevice, c->stream));
-        GOSH_HIP(hipMemsetAsync(ctr.p, 0, sizeof(unsigned long long) * (njobs + 1), c->stream));
-        PersistArgs A{};
-        A.jobs = dj.p;
-        A.njobs = njobs;
-        A.k = k;
-        A.key0 = key0;
-        A.key1 = key1;
-        A.chunk = chunk;
-        A.round_start = drs.p;
-        A.round_jobs = dact.p;
-        A.job_task0 = dt0.p;
-        A.max_e = max_e;
-        A.next_task = ctr.p + njobs;
-        A.done = ctr.p;
-        A.updates = updates;
-        A.error = reinterpret_cast<unsigned int*>(static_cast<char*>(c->scratch) + 256);
-        A.spin_limit = 1ull << 22;   // a few seconds of polling
-        int cus = 0;
-        GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-        // no more waves than tasks in the first (largest) epoch round: extra
-        // waves could only poll the done counters of epochs not yet reached
-        const int64_t round0 = round_start[1] - round_start[0];
-        const int64_t waves = std::min<int64_t>(static_cast<int64_t>(cus) * R.blocks_per_cu * (kBlock / 64), round0);
-        const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, ceil_div(waves, kBlock / 64)));
-        void* args[] = {&A};
-        GOSH_HIP(hipLaunchKernel(K.persist, dim3(blocks), dim3(kBlock), args, 0, c->stream));
+        PersistTables T{dj.p, drs.p, dt0.p, dact.p, ctr.p,
+                        reinterpret_cast<unsigned int*>(static_cast<char*>(c->scratch) + 256)};
+        launch_persistent(c, jobs, active, R, K, k, updates, T);
         // the small buffers above are released to the context cache only; the
         // stream orders their reuse after this launch
     } else {
@@ -495,16 +544,13 @@ void save_tune_entry(const std::string& key, const RunShape& R) {
     std::fclose(f);
 }
 
-}  // namespace
-
-void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
-                   uint64_t* updates_dev, int32_t* chosen) {
+// Checks the job list of a batched call and keeps the jobs with work.
+std::vector<gosh_job> checked_jobs(const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k) {
     GOSH_REQUIRE(njobs >= 0 && (njobs == 0 || jobs), GOSH_E_INVALID_ARG, "bad job list");
     GOSH_REQUIRE(dt == GOSH_F32 || dt == GOSH_BF16, GOSH_E_INVALID_ARG, "dtype must be F32 or BF16");
     GOSH_REQUIRE(d == 8 || d == 16 || d == 32 || d == 64 || d == 128 || d == 256, GOSH_E_INVALID_ARG,
                  "d must be one of 8, 16, 32, 64, 128, 256");
     GOSH_REQUIRE(k >= 0 && k <= 15, GOSH_E_INVALID_ARG, "k must be in [0, 15]");
-    GOSH_REQUIRE(mode >= GOSH_BATCH_AUTO && mode <= GOSH_BATCH_EPOCH_GRAPH, GOSH_E_INVALID_ARG, "bad batch mode");
     std::vector<gosh_job> kept;
     for (int i = 0; i < njobs; ++i) {
         const gosh_job& q = jobs[i];
@@ -517,13 +563,26 @@ void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d
         GOSH_REQUIRE(q.g.n == 0 || q.emb, GOSH_E_INVALID_ARG, "null job embedding");
         if (q.g.n > 0 && q.epochs > 0) kept.push_back(q);
     }
+    return kept;
+}
+
+}  // namespace
+
+void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
+                   uint64_t* updates_dev, int32_t* chosen) {
+    GOSH_REQUIRE(mode >= GOSH_BATCH_AUTO && mode <= GOSH_BATCH_EPOCH_GRAPH, GOSH_E_INVALID_ARG, "bad batch mode");
+    std::vector<gosh_job> kept = checked_jobs(jobs, njobs, dt, d, k);
     if (chosen) chosen[0] = chosen[1] = chosen[2] = 0;
     if (kept.empty()) return;
     const Kernels K = dt == GOSH_BF16 ? pick_d<true>(d, k) : pick_d<false>(d, k);
     Plan P;
     build_plan(c, kept.data(), static_cast<int>(kept.size()), P);
     RunShape R{GOSH_BATCH_PERSISTENT, 2, 4};
-    if (mode == GOSH_BATCH_EPOCH_GRAPH) {
+    if (c->deterministic) {
+        // each job epoch one task visited in source order: per job exactly
+        // gosh_train's deterministic mode; jobs still run side by side
+        R = {GOSH_BATCH_PERSISTENT, 2, 0};
+    } else if (mode == GOSH_BATCH_EPOCH_GRAPH) {
         R = {GOSH_BATCH_EPOCH_GRAPH, 0, 0};
     } else if (mode == GOSH_BATCH_AUTO) {
         load_tune_file(c);

@@ -513,7 +513,19 @@ def gosh_train_batched(ctx: Context, jobs, k: int, mode: int = GOSH_BATCH_AUTO,
     Returns the execution used: (mode, blocks per CU, chunk length)."""
     if not jobs:
         return (0, 0, 0)
-    arr = (gosh_job * len(jobs))()
+    arr, code, d = _job_array(jobs)
+    chosen = (C.c_int32 * 3)()
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    ctx.check(lib().gosh_train_batched(ctx.h, arr, len(jobs), code, d, k, mode, u, chosen))
+    return tuple(chosen)
+
+
+def _job_array(jobs):
+    """(gosh_job array, dtype code, d) of a list of (CSR or gosh_csr view, emb,
+    epochs, lr, level, tag)."""
+    arr = (gosh_job * max(len(jobs), 1))()
+    if not jobs:
+        return arr, GOSH_F32, 8
     dtype = jobs[0][1].dtype
     d = jobs[0][1].shape[1]
     for i, (g, emb, epochs, lr, level, tag) in enumerate(jobs):
@@ -521,10 +533,7 @@ def gosh_train_batched(ctx: Context, jobs, k: int, mode: int = GOSH_BATCH_AUTO,
         if emb.dtype != dtype or emb.dim() != 2 or emb.shape[1] != d or emb.shape[0] != view.n:
             raise ValueError("every job needs a [n, d] embedding of the same dtype and d")
         arr[i] = gosh_job(view, _dev(emb, name="emb").value, epochs, lr, level, tag)
-    chosen = (C.c_int32 * 3)()
-    u = _dev(updates, torch.int64, "updates") if updates is not None else None
-    ctx.check(lib().gosh_train_batched(ctx.h, arr, len(jobs), _dtype_code(jobs[0][1]), d, k, mode, u, chosen))
-    return tuple(chosen)
+    return arr, _dtype_code(jobs[0][1]), d
 
 
 # ------------------------------------------------------------------ partitioned embedding (Section 5)

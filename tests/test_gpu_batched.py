@@ -35,11 +35,80 @@ def test_lr_zero_is_identity(gctx, mode):
         assert torch.equal(M, R)
 
 
+def _rel_rows(a, b):
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+    return float((num / den).max()) if len(a) else 0.0
+
+
+def _bf16_to_dev(orc, f):
+    bits = orc.f32_to_bf16_rne(f).reshape(f.shape)
+    return torch.from_numpy(bits.view(np.int16).copy()).view(torch.bfloat16).cuda(), bits
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_deterministic_jobs_match_oracle(gctx, orc, dtype):
+    """Deterministic mode: every job equals the sequential oracle (Algorithm 3
+    in source order with the job's own epochs, lr, level and tag): FP32 within
+    1e-4 relative per row, BF16 within 2e-2 per row; and bit for bit the rows
+    of gosh_train in deterministic mode on the job's graph."""
+    from paper_2110_10049_amd import gosh as G
+    print(f"[batched] deterministic {dtype}", flush=True)
+    bf = dtype == torch.bfloat16
+    rng = np.random.default_rng(11)
+    specs = []
+    for j in range(12):
+        off, idx = rmat_csr(6 + j % 4, 4 + j % 5, seed=300 + j)     # some with isolated vertices
+        specs.append((off, idx, int(rng.integers(1, 9)), float(rng.uniform(0.01, 0.05)), j % 3, 7 * j))
+    off2, idx2 = np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32)
+    specs.append((off2, idx2, 40, 0.5, 0, 999))                       # K_2: epochs chain strongly
+    d, k = 32, 3
+    jobs, inits, solo = [], [], []
+    for j, (off, idx, ep, lr, level, tag) in enumerate(specs):
+        n = len(off) - 1
+        f = init_rows(n, d, 50 + j) * (40 if j == len(specs) - 1 else 8)
+        if bf:
+            M, bits = _bf16_to_dev(orc, f)
+            inits.append(bits)
+        else:
+            M = torch.from_numpy(f).cuda()
+            inits.append(f)
+        jobs.append((G.CSR.from_numpy(off, idx), M, ep, lr, level, tag))
+        solo.append(M.clone())
+    gctx.set_deterministic(True)
+    try:
+        chosen = G.gosh_train_batched(gctx, jobs, k, G.GOSH_BATCH_AUTO)
+        for (g, _, ep, lr, level, tag), S in zip(jobs, solo):
+            # gosh_train on the job's graph: level and tag go into the Philox counter
+            lv = G.gosh_levels_single(gctx, g)
+            if level == 0:
+                G.gosh_train(gctx, lv, 0, S, ep, lr, k, tag=tag)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_deterministic(False)
+    assert chosen[0] == G.GOSH_BATCH_PERSISTENT and chosen[2] == 0
+    for j, ((off, idx, ep, lr, level, tag), J, S) in enumerate(zip(specs, jobs, solo)):
+        Mo = inits[j].copy() if bf else inits[j].astype(np.float64)
+        orc.train(off, idx, Mo, ep, float(np.float32(lr)), k, 4, level=level, tag=tag)
+        if bf:
+            got = orc.bf16_to_f64(J[1].cpu().view(torch.int16).numpy().view(np.uint16))
+            want = orc.bf16_to_f64(Mo)
+            assert _rel_rows(got, want) < 2e-2, j
+        else:
+            got = J[1].cpu().numpy().astype(np.float64)
+            assert _rel_rows(got, Mo) < 1e-4, j
+        if level == 0:
+            assert torch.equal(J[1].view(torch.int16) if bf else J[1], S.view(torch.int16) if bf else S), j
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 def test_k2_jobs_match_per_job_training(gctx, mode, dtype):
-    # Each K_2 job's epochs depend on the previous ones; overlapping epochs
-    # inside one launch would show up as a large difference.
+    # Scheduling check of the concurrent executions: each K_2 job's epochs
+    # depend on the previous ones, so epochs overlapping inside one launch
+    # would show up as a large difference from per-job launches (one epoch
+    # per launch).  (The oracle comparison of the batched trainer is
+    # test_deterministic_jobs_match_oracle.)
     from paper_2110_10049_amd import gosh as G
     print(f"[batched] k2 {mode} {dtype}", flush=True)
     g = _k2(G)
@@ -115,7 +184,7 @@ def test_auc_matches_oracle_per_job(gctx, orc, mode):
         a_o = evaluate_auc(Mo, sp, seed=5)
         print(f"[batched] job {j} AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
         assert a_o > 0.85
-        assert abs(a_g - a_o) < 0.015
+        assert abs(a_g - a_o) < 0.01
 
 
 def test_autotune_choice_is_valid_and_cached(gctx):

@@ -134,7 +134,7 @@ def test_overlap_with_zero_lr_is_identity(gctx):
 
 def test_plain_negative_stores_keep_auc_on_large_levels(gctx, orc):
     # negatives stored plainly (the paper's lock-free writes) on levels of at
-    # least 8192 vertices: same update count, AUC within 0.015 of the oracle
+    # least 8192 vertices: same update count, AUC within 0.01 of the oracle
     from paper_2110_10049_amd import gosh as G
     from paper_2110_10049_amd.driver import EmbedConfig, embed
     sp = train_split(16, 16)
@@ -152,7 +152,7 @@ def test_plain_negative_stores_keep_auc_on_large_levels(gctx, orc):
     a_g = evaluate_auc(res.emb.cpu().numpy(), sp, seed=5)
     a_o = evaluate_auc(Mo, sp, seed=5)
     print(f"[e2e plain negatives] n0={res.sizes[0]} AUC gpu={a_g:.4f} oracle={a_o:.4f}", flush=True)
-    assert abs(a_g - a_o) < 0.015
+    assert abs(a_g - a_o) < 0.01
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
