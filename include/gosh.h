@@ -328,6 +328,26 @@ gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t
                                gosh_dtype dt, int32_t d, int32_t k, gosh_batch_mode mode,
                                uint64_t* updates_dev, int32_t* chosen_out);
 
+/* gosh_train_batched for callers that cannot allocate device memory (code
+ * recorded into a HIP graph by stream capture, tight serving loops, hosts
+ * that forbid allocation during a run): the same persistent execution, with
+ * no hipMalloc, hipFree or other allocating call.  Its device tables (job
+ * table, per-round task starts, per-job done counters, task counter, error
+ * word) live in a static device array of 524,800 bytes that every GPU the library
+ * runs on holds until the process ends, set up by gosh_ctx_create.  Limits:
+ * at most 4096 jobs with work and at most 16384 epochs per job
+ * (GOSH_E_INVALID_ARG beyond).  Every call on a GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (from several contexts or
+ * streams) race and must not be issued; each call clears the counters it
+ * uses.  Jobs, rows, dtype, d, k and the update counter as
+ * gosh_train_batched; the execution is GOSH_BATCH_PERSISTENT (2 blocks per
+ * CU, tasks of 4 waves' sources), or in deterministic mode each job epoch
+ * one task visited in source order (then every job equals gosh_train in
+ * deterministic mode).  Synchronous (it waits for the stream to read the
+ * error word); a scheduling failure returns GOSH_E_DEVICE. */
+gosh_status gosh_train_batched_noalloc(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs, gosh_dtype dt,
+                                       int32_t d, int32_t k, uint64_t* updates_dev);
+
 /* ExpandEmbedding (Algorithm 2): every vertex v of level fine_level starts
  * from the trained row of its super vertex.  mlp == NULL: copy,
  * fine[v] = coarse[map_{fine_level}[v]] (bit-exact).  Otherwise the learned

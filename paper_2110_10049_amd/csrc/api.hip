@@ -159,6 +159,7 @@ gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream, uint64_
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->scratch = c->alloc(4096);
         GOSH_HIP(hipMemsetAsync(c->scratch, 0, 4096, c->stream));
+        gosh::batched_noalloc_init(device);
     });
     if (st != GOSH_OK) {
         gosh_ctx_destroy(ctx);
@@ -491,6 +492,18 @@ gosh_status gosh_train_batched(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t
         unsigned int err = 0;
         GOSH_HIP(hipMemcpy(&err, static_cast<char*>(c->scratch) + 256, 4, hipMemcpyDeviceToHost));
         GOSH_REQUIRE(err == 0, GOSH_E_DEVICE, "batched training: a task waited beyond the spin limit");
+    });
+}
+
+gosh_status gosh_train_batched_noalloc(gosh_ctx* ctx, const gosh_job* jobs_host, int32_t njobs, gosh_dtype dt,
+                                       int32_t d, int32_t k, uint64_t* updates_dev) {
+    if (!ctx) return GOSH_E_INVALID_ARG;
+    return guarded(ctx, [&] {
+        Ctx* c = &ctx->c;
+        set_device(c);
+        gosh::train_batched_noalloc(c, jobs_host, njobs, dt, d, k, updates_dev);
+        GOSH_REQUIRE(gosh::batched_noalloc_error(c) == 0, GOSH_E_DEVICE,
+                     "batched training: a task waited beyond the spin limit");
     });
 }
 

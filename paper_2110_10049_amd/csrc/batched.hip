@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -566,7 +567,113 @@ std::vector<gosh_job> checked_jobs(const gosh_job* jobs, int njobs, gosh_dtype d
     return kept;
 }
 
+// ---------------------------------------------------------------- no-allocation entry
+// The device tables of gosh_train_batched_noalloc live in this file-scope
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only names a stand-in
+// symbol): its device address is looked up once per device and kept in
+// g_scratch_dev.
+constexpr int kNoAllocMaxJobs = 4096;
+constexpr int kNoAllocMaxEpochs = 16384;
+constexpr size_t kTabJobs = 0;
+constexpr size_t kTabRounds = kTabJobs + sizeof(BJob) * kNoAllocMaxJobs;
+constexpr size_t kTabTask0 = kTabRounds + sizeof(int64_t) * (kNoAllocMaxEpochs + 1);
+constexpr size_t kTabActive = kTabTask0 + sizeof(int64_t) * (kNoAllocMaxJobs + 1);
+constexpr size_t kTabCtr = (kTabActive + sizeof(int32_t) * kNoAllocMaxEpochs + 255) / 256 * 256;
+constexpr size_t kTabEnd = kTabCtr + sizeof(unsigned long long) * (kNoAllocMaxJobs + 2);   // + error word
+constexpr size_t kScratchBytes = (kTabEnd + 255) / 256 * 256;
+static_assert(kTabRounds % 8 == 0 && kTabTask0 % 8 == 0 && kTabActive % 8 == 0, "table alignment");
+static_assert(sizeof(BJob) == 64 && kScratchBytes == 524800, "size stated in gosh.h");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
 }  // namespace
+
+void batched_noalloc_init(int device) {
+    GOSH_REQUIRE(device >= 0 && device < kMaxDevices, GOSH_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return;
+    void* ptr = nullptr;
+    // called with `device` current: its own copy of the array
+    GOSH_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    GOSH_REQUIRE(ptr != nullptr, GOSH_E_DEVICE, "no device address for the batched scratch array");
+    g_scratch_dev[device] = ptr;
+}
+
+void train_batched_noalloc(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k,
+                           uint64_t* updates_dev) {
+    std::vector<gosh_job> kept = checked_jobs(jobs, njobs, dt, d, k);
+    GOSH_REQUIRE(kept.size() <= static_cast<size_t>(kNoAllocMaxJobs), GOSH_E_INVALID_ARG,
+                 "gosh_train_batched_noalloc takes at most 4096 jobs with work");
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = static_cast<char*>(c->device >= 0 && c->device < kMaxDevices ? g_scratch_dev[c->device] : nullptr);
+    }
+    GOSH_REQUIRE(base, GOSH_E_DEVICE, "batched scratch array not set up on this device");
+    std::vector<BJob> bj(kept.size());
+    for (size_t i = 0; i < kept.size(); ++i) {
+        const gosh_job& q = kept[i];
+        BJob& J = bj[i];
+        J.offsets = q.g.offsets;
+        J.indices = q.g.indices;
+        J.emb = q.emb;
+        J.n = q.g.n;
+        J.nnz = q.g.nnz;
+        J.lr = q.lr;
+        J.epochs = q.epochs;
+        J.w2 = stream_word2(q.level, q.tag);
+        J.off64 = q.g.offsets_is_i64 ? 1 : 0;
+        J.nchunks = 0;
+    }
+    std::stable_sort(bj.begin(), bj.end(), [](const BJob& a, const BJob& b) { return a.epochs > b.epochs; });
+    const int max_e = bj.empty() ? 0 : bj[0].epochs;
+    GOSH_REQUIRE(max_e <= kNoAllocMaxEpochs, GOSH_E_INVALID_ARG,
+                 "gosh_train_batched_noalloc takes at most 16384 epochs per job");
+    // error word first (one 64-bit slot), then the done counters and the task counter
+    PersistTables T{reinterpret_cast<BJob*>(base + kTabJobs), reinterpret_cast<int64_t*>(base + kTabRounds),
+                    reinterpret_cast<int64_t*>(base + kTabTask0), reinterpret_cast<int32_t*>(base + kTabActive),
+                    reinterpret_cast<unsigned long long*>(base + kTabCtr + sizeof(unsigned long long)),
+                    reinterpret_cast<unsigned int*>(base + kTabCtr)};
+    // a call keeps the array's last contents: clear the error word (and the counters)
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
+                       reinterpret_cast<unsigned long long*>(base + kTabCtr), static_cast<int64_t>(bj.size() + 2));
+    GOSH_HIP(hipGetLastError());
+    if (bj.empty()) return;
+    std::vector<int32_t> active(max_e);
+    for (int e = 0; e < max_e; ++e) {
+        int a = 0;
+        while (a < static_cast<int>(bj.size()) && bj[a].epochs > e) ++a;
+        active[e] = a;
+    }
+    const Kernels K = dt == GOSH_BF16 ? pick_d<true>(d, k) : pick_d<false>(d, k);
+    const RunShape R = c->deterministic ? RunShape{GOSH_BATCH_PERSISTENT, 2, 0} : RunShape{GOSH_BATCH_PERSISTENT, 2, 4};
+    auto* upd = reinterpret_cast<unsigned long long*>(updates_dev);
+    // launch_persistent clears the counters again (the same words) before its launch
+    launch_persistent(c, bj, active, R, K, k, upd, T);
+    if (upd) {
+        hipLaunchKernelGGL(k_add_job_updates, dim3(static_cast<unsigned>(bj.size())), dim3(256), 0, c->stream, T.jobs,
+                           k, upd);
+        GOSH_HIP(hipGetLastError());
+    }
+}
+
+unsigned int batched_noalloc_error(Ctx* c) {
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = static_cast<char*>(c->device >= 0 && c->device < kMaxDevices ? g_scratch_dev[c->device] : nullptr);
+    }
+    GOSH_REQUIRE(base, GOSH_E_DEVICE, "batched scratch array not set up on this device");
+    GOSH_HIP(hipStreamSynchronize(c->stream));
+    unsigned int err = 0;
+    GOSH_HIP(hipMemcpy(&err, base + kTabCtr, sizeof(err), hipMemcpyDeviceToHost));
+    return err;
+}
 
 void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
                    uint64_t* updates_dev, int32_t* chosen) {

@@ -170,6 +170,11 @@ void prolong_copy(Ctx* c, const Level& fine, const void* coarse, void* fine_emb,
                   int d);
 void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k, int mode,
                    uint64_t* updates_dev, int32_t* chosen);
+// the no-allocation variant: tables in a static device array set up per device
+void batched_noalloc_init(int device);
+void train_batched_noalloc(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d, int k,
+                           uint64_t* updates_dev);
+unsigned int batched_noalloc_error(Ctx* c);   // waits for the stream
 void free_level(Ctx* c, Level& L);
 // (partition.hip)
 void train_partitioned(Ctx* c, const gosh_csr* g_host, void* emb_host, gosh_dtype dt, int d, int epochs,

@@ -106,6 +106,8 @@ _SIGNATURES = [
                                   C.c_int64, C.POINTER(C.c_int64)]),
     ("gosh_train_batched", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
                                      C.c_int, _P, C.POINTER(C.c_int32)]),
+    ("gosh_train_batched_noalloc", C.c_int, [_P, C.POINTER(gosh_job), C.c_int32, C.c_int, C.c_int32, C.c_int32,
+                                             _P]),
     ("gosh_prolong", C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_int, C.c_int32, _P]),
     ("gosh_train_partitioned", C.c_int, [_P, C.POINTER(gosh_csr), _P, C.c_int, C.c_int32, C.c_int32, C.c_float,
                                          C.c_int32, C.c_int32, C.c_uint32, C.POINTER(gosh_part_params), _P,
@@ -534,6 +536,14 @@ def _job_array(jobs):
             raise ValueError("every job needs a [n, d] embedding of the same dtype and d")
         arr[i] = gosh_job(view, _dev(emb, name="emb").value, epochs, lr, level, tag)
     return arr, _dtype_code(jobs[0][1]), d
+
+
+def gosh_train_batched_noalloc(ctx: Context, jobs, k: int, updates: torch.Tensor | None = None):
+    """gosh_train_batched without any device allocation by the library (its
+    tables live in a static device array); jobs as gosh_train_batched."""
+    arr, code, d = _job_array(jobs)
+    u = _dev(updates, torch.int64, "updates") if updates is not None else None
+    ctx.check(lib().gosh_train_batched_noalloc(ctx.h, arr, len(jobs), code, d, k, u))
 
 
 # ------------------------------------------------------------------ partitioned embedding (Section 5)
