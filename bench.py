@@ -20,8 +20,17 @@ time.  roofline: the dominant kernel is the level-0 training epoch; its
 algorithmic bytes per source are 2*d*b*(2+k) + 2*o + 4 (source row read and
 written, 1+k sample rows read and written, two offsets and one index), and
 its launch duration comes from events around level-0 training inside the
-timed steps.  cpu_baseline: the FP64 oracle's sequential trainer on a
-bounded sample of the same level-0 graph, single-threaded on the host.
+timed steps; cache_served flags rows that fit in the 256 MiB MALL (the BF16
+rows of this graph do), so roofline_scale22 repeats the level-0 epoch on a
+scale-22 graph whose rows do not.  Also reported: every level's time,
+updates and edge-samples/s, the coarsening's time, edges/s and fraction of
+its algorithmic bytes, link-prediction AUC of both dtypes against the FP64
+oracle's stored result for the same seeds and evaluation pairs, the AUC of
+the degree product alone, AUC in the paper's epoch unit (|E| updates), and
+the running loss of every level's last epoch beside the oracle's.
+cpu_baseline: the FP64 oracle's trainer on the level-0 graph with each
+epoch's sources over all host cores (OpenMP, Hogwild), the single-threaded
+sequential oracle beside it.
 """
 from __future__ import annotations
 
@@ -39,6 +48,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_bf16_traffic.md")
+FP32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_epoch_rmat20_fp32_traffic.md")
 WALK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_update_walk20_bf16_traffic.md")
 MLP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "prolong_forward_mlp22_bf16_traffic.md")
 
@@ -103,6 +113,8 @@ def parse():
                     help="plain stores for negative rows on levels of at least this many vertices (0: atomic adds "
                          "everywhere)")
     ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--no-loss", action="store_true", help="skip the untimed running-loss passes")
+    ap.add_argument("--no-big-roofline", action="store_true", help="skip the scale-22 level-0 roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-epochs", type=int, default=10)
@@ -672,11 +684,37 @@ def main():
         return big_workload(a)
     if a.workload == "walk20":
         return walk_workload(a)
+    return main_workload(a)
+
+
+MALL_BYTES = 256 << 20
+GOLD_C2 = os.path.join(ROOT, "tests", "golden", "e2e_auc_rmat20.json")
+
+
+def coarsening_bytes(shapes, o):
+    """Algorithmic HBM bytes of coarsening every level (read the CSR, gather
+    the map of every entry, write the map, write the next CSR)."""
+    tot = 0
+    for (n, nnz), (n2, nnz2) in zip(shapes[:-1], shapes[1:]):
+        tot += o * n + 4 * nnz + 4 * nnz + 4 * n + o * n2 + 4 * nnz2
+    return tot
+
+
+def degree_product_auc(offsets, pairs):
+    """AUC of the score deg(u) * deg(v) on the evaluator's test pairs (no
+    embedding): how much of link prediction on the graph degree alone explains."""
+    from sklearn.metrics import roc_auc_score
+    deg = np.diff(offsets).astype(np.float64)
+    return float(roc_auc_score(pairs.yte, deg[pairs.xte[:, 0]] * deg[pairs.xte[:, 1]]))
+
+
+def main_workload(a):
     import torch
 
     from paper_2110_10049_amd import gosh as G
     from paper_2110_10049_amd.driver import EmbedConfig, embed
-    from synth import evaluate_auc, init_rows, rmat_csr, split_edges
+    from synth import init_rows, rmat_csr, split_edges
+    from synth.linkpred import auc_on_pairs, make_eval_pairs
 
     scale, ef, d, k, epochs, threshold = WORKLOADS[a.workload]
     if a.dim:
@@ -696,25 +734,32 @@ def main():
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
 
-    def run(dtype, steps, warmup):
-        cfg = EmbedConfig(d=d, epochs=epochs, p=p, lr=lr, k=k, dtype=dtype, threshold=threshold,
-                          batch_levels_upto=a.batch_levels_upto,
-                          batch_mode={"auto": G.GOSH_BATCH_AUTO, "persistent": G.GOSH_BATCH_PERSISTENT,
-                                      "graph": G.GOSH_BATCH_EPOCH_GRAPH}[a.batch_mode])
-        lv = G.gosh_coarsen(ctx, g, threshold)
-        # the lock-and-skip mapping's coarsest size varies from run to run:
-        # keep the first rows of a larger draw resident (init_rows(n) is a
-        # prefix of init_rows(N) for n <= N)
-        n_c = lv.sizes()[-1] * (4 if a.coarsen == "lock-skip" else 1)
-        f = init_rows(n_c, d, seeds["init"])
-        init_dev = torch.from_numpy(f).cuda().to(dtype)   # RNE to BF16, resident before timing
-        del lv
+    def config(dtype, unit="passes"):
+        return EmbedConfig(d=d, epochs=epochs, p=p, lr=lr, k=k, dtype=dtype, threshold=threshold,
+                           batch_levels_upto=a.batch_levels_upto, epoch_unit=unit,
+                           batch_mode={"auto": G.GOSH_BATCH_AUTO, "persistent": G.GOSH_BATCH_PERSISTENT,
+                                       "graph": G.GOSH_BATCH_EPOCH_GRAPH}[a.batch_mode])
+
+    lv0 = G.gosh_coarsen(ctx, g, threshold)
+    n_c = lv0.sizes()[-1] * (4 if a.coarsen == "lock-skip" else 1)
+    del lv0
+    # the lock-and-skip mapping's coarsest size varies from run to run: keep
+    # the first rows of a larger draw resident (init_rows(n) is a prefix of
+    # init_rows(N) for n <= N)
+    init32 = torch.from_numpy(init_rows(n_c, d, seeds["init"])).cuda()
+
+    def init_for(dtype):
+        dev = init32.to(dtype)      # RNE to BF16, resident before timing
 
         def init_fn(n, dd):
             if n > n_c:
                 raise RuntimeError(f"coarsest level has {n} vertices, more than the {n_c} prepared rows")
-            return init_dev[:n].clone()
+            return dev[:n].clone()
+        return init_fn
 
+    def run(dtype, steps, warmup):
+        cfg = config(dtype)
+        init_fn = init_for(dtype)
         for _ in range(warmup):
             embed(ctx, g, cfg, init_fn)
         torch.cuda.synchronize()
@@ -726,19 +771,23 @@ def main():
         wall = time.perf_counter() - t_start
         updates = sum(int(r.updates.item()) for r in results)
         last = results[-1]
-        lvl0 = [r.timings["train_events"][0] for r in results]
-        l0_ms = float(np.mean([s.elapsed_time(e) for s, e in lvl0]))
-        train_ms = float(np.mean([sum(s.elapsed_time(e) for s, e in r.timings["train_events"].values())
-                                  for r in results]))
+        D = len(last.sizes)
+        lvl_ms = [float(np.mean([r.timings["train_events"][i][0].elapsed_time(r.timings["train_events"][i][1])
+                                 for r in results])) for i in range(D)]
+        lvl_upd = [int(last.level_updates[i].item()) for i in range(D)]
+        coarsen_ms = float(np.mean([r.timings["coarsen_events"][0].elapsed_time(r.timings["coarsen_events"][1])
+                                    for r in results]))
+        shapes = [last.levels.shape(i) for i in range(D)]
         return {
             "wall_s": wall, "ms_per_step": 1e3 * wall / steps, "updates_per_step": updates // steps,
-            "value": updates / wall, "sizes": last.sizes, "schedule": last.schedule,
-            "level0_ms": l0_ms, "train_ms": train_ms, "emb": last.emb,
+            "value": updates / wall, "sizes": last.sizes, "schedule": last.schedule, "shapes": shapes,
+            "level_ms": lvl_ms, "level_updates": lvl_upd, "level0_ms": lvl_ms[0], "train_ms": sum(lvl_ms),
+            "coarsen_ms": coarsen_ms, "emb": last.emb,
         }
 
     bf = run(torch.bfloat16, a.steps, a.warmup)
     log(f"bf16: {bf['ms_per_step']:.2f} ms/step, {bf['value'] / 1e9:.3f} G edge-samples/s, "
-        f"level0 {bf['level0_ms']:.2f} ms, levels {bf['sizes']}")
+        f"level0 {bf['level0_ms']:.2f} ms, coarsening {bf['coarsen_ms']:.2f} ms, levels {bf['sizes']}")
     f32 = None
     if not a.no_fp32:
         f32 = run(torch.float32, max(2, a.steps // 2), 1)
@@ -757,7 +806,29 @@ def main():
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_train level 0", "bytes_per_launch": bytes_launch,
-                "launch_us": round(launch_s * 1e6, 2)}
+                "launch_us": round(launch_s * 1e6, 2),
+                # a level whose rows fit in the 256 MiB MALL may be served partly from it
+                "cache_served": n0 * d * b <= MALL_BYTES, "rows_bytes": n0 * d * b}
+
+    def per_level(r, b):
+        out = []
+        for i, n in enumerate(r["sizes"]):
+            per_src = 2 * d * b * (2 + k) + 2 * o + 4
+            sec = r["level_ms"][i] / 1e3
+            out.append({"n": n, "nnz": r["shapes"][i][1], "epochs": r["schedule"][i], "ms": round(r["level_ms"][i], 3),
+                        "updates": r["level_updates"][i],
+                        "edge_samples_per_s": round(r["level_updates"][i] / sec, 1) if sec > 0 else None,
+                        "hbm_frac": round(n * per_src * r["schedule"][i] / sec / 1e9 / HBM_PEAK_GBS, 4)
+                        if sec > 0 else None})
+        return out
+
+    def coarsening(r):
+        cb = coarsening_bytes(r["shapes"], o)
+        sec = r["coarsen_ms"] / 1e3
+        edges = sum(nnz for _, nnz in r["shapes"][:-1])
+        return {"ms": round(r["coarsen_ms"], 3), "edges_per_s": round(edges / sec, 1),
+                "algorithmic_bytes": cb, "achieved_gbs": round(cb / sec / 1e9, 1),
+                "hbm_frac": round(cb / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": "edge-samples/s (executed UpdateEmbed calls) of the whole hot path at d=128",
@@ -770,37 +841,128 @@ def main():
         "config": {"workload": f"R-MAT scale {scale} ef {ef} link-prediction train graph "
                                f"(|V|={n0}, nnz={len(sp.indices)}), d={d}, k={k}, e={epochs}, p={p}, "
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
-                   "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds,
+                   "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds, "epoch_unit": "passes",
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
                    "plain_negative_stores_min_vertices": a.plain_neg_min, "coarsening": a.coarsen,
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),
+        "levels": per_level(bf, 2),
+        "coarsening": coarsening(bf),
     }
     if f32 is not None:
         out["fp32"] = {"value": round(f32["value"], 1), "ms_per_step": round(f32["ms_per_step"], 3),
-                       "train_ms_per_step": round(f32["train_ms"], 3), "roofline": roof(f32, 4)}
+                       "train_ms_per_step": round(f32["train_ms"], 3),
+                       "roofline": roof(f32, 4, measured_traffic(FP32_TRAFFIC_FILE)
+                                        if a.workload == "rmat20" and d == 128 else None),
+                       "levels": per_level(f32, 4)}
+    if a.workload == "rmat20" and d == 128 and not a.no_big_roofline:
+        out["roofline_scale22"] = scale22_roofline(ctx, d, k, lr, seeds)
+    gold = None
+    if a.workload == "rmat20" and d == 128 and os.path.exists(GOLD_C2):
+        gold = json.load(open(GOLD_C2))
     if not a.no_auc:
         t = time.time()
-        out["auc"] = {"bf16": round(evaluate_auc(bf["emb"].float().cpu().numpy(), sp, seeds["eval"],
-                                                 max_train=200_000), 4)}
+        ev = gold["config"]["eval"] if gold else {"max_train": 200_000, "max_test": 1_000_000}
+        pairs = make_eval_pairs(sp, seeds["eval"], ev["max_train"], ev["max_test"])
+        auc = {"bf16": round(auc_on_pairs(bf["emb"].float().cpu().numpy(), pairs), 4),
+               "eval": {"max_train": ev["max_train"], "max_test": ev["max_test"]},
+               "degree_product": round(degree_product_auc(sp.offsets, pairs), 4)}
         if f32 is not None:
-            out["auc"]["fp32"] = round(evaluate_auc(f32["emb"].cpu().numpy(), sp, seeds["eval"],
-                                                    max_train=200_000), 4)
-        log(f"auc {out['auc']} ({time.time() - t:.1f}s)")
+            auc["fp32"] = round(auc_on_pairs(f32["emb"].cpu().numpy(), pairs), 4)
+            auc["bf16_minus_fp32"] = round(auc["bf16"] - auc["fp32"], 4)
+        if gold:
+            auc["oracle"] = {"bf16": gold["bf16"]["auc"], "fp64": gold["fp64"]["auc"],
+                             "source": "tests/golden/e2e_auc_rmat20.json (FP64 oracle, same seeds and pairs)"}
+            auc["gpu_minus_oracle"] = {"bf16": round(auc["bf16"] - gold["bf16"]["auc"], 4)}
+            if "fp32" in auc:
+                auc["gpu_minus_oracle"]["fp32"] = round(auc["fp32"] - gold["fp64"]["auc"], 4)
+            auc["gpu_within_0.01_of_oracle"] = all(abs(v) < 0.01 for v in auc["gpu_minus_oracle"].values())
+            # stochastic rounding's own effect on the method's AUC, as the oracle shows it
+            auc["oracle_bf16_minus_fp64"] = round(gold["bf16"]["auc"] - gold["fp64"]["auc"], 4)
+        # the paper's epoch unit (one epoch = |E| updates), one untimed BF16
+        # pass; at lr 0.045 its dense coarse levels (thousands of passes)
+        # drive the rows to overflow, as the sequential FP64 oracle does on
+        # the same level, so the pass reports whether its rows stayed finite
+        t1 = time.perf_counter()
+        r_e = embed(ctx, g, config(torch.bfloat16, "edges"), init_for(torch.bfloat16))
+        torch.cuda.synchronize()
+        sec_e = time.perf_counter() - t1
+        finite = bool(torch.isfinite(r_e.emb.float()).all().item())
+        auc["edges_unit"] = {"bf16": round(auc_on_pairs(r_e.emb.float().cpu().numpy(), pairs), 4) if finite else None,
+                             "rows_finite": finite, "schedule": list(r_e.schedule),
+                             "updates": int(r_e.updates.item()), "seconds": round(sec_e, 3),
+                             "edge_samples_per_s": round(int(r_e.updates.item()) / sec_e, 1)}
+        del r_e
+        log(f"auc {auc} ({time.time() - t:.1f}s)")
+        out["auc"] = auc
+    if not a.no_loss:
+        # running loss (Section 2's objective over each epoch's updates), one untimed pass per dtype
+        loss = {}
+        for name, dtype in (("bf16", torch.bfloat16), ("fp32", torch.float32)):
+            r_l = embed(ctx, g, config(dtype), init_for(dtype), record_loss=True)
+            torch.cuda.synchronize()
+            loss[name] = [round(float(r_l.losses[i][-1].item()), 2) for i in range(len(r_l.sizes))]
+        if gold:
+            loss["oracle"] = {"bf16": [round(x, 2) for x in gold["bf16"]["last_epoch_loss"]],
+                              "fp64": [round(x, 2) for x in gold["fp64"]["last_epoch_loss"]]}
+        out["loss_last_epoch_per_level"] = loss
     if not a.no_cpu_baseline:
         import oracle
+        cores = len(os.sched_getaffinity(0))
         M = init_rows(n0, d, seeds["init"]).astype(np.float64)
         oracle.train(sp.offsets, sp.indices, M, 1, lr, k, seeds["philox"], level=0)  # page in
         t = time.perf_counter()
-        upd = oracle.train(sp.offsets, sp.indices, M, a.cpu_sample_epochs, lr, k, seeds["philox"], level=0)
+        upd1 = oracle.train(sp.offsets, sp.indices, M, a.cpu_sample_epochs, lr, k, seeds["philox"], level=0)
+        dt1 = time.perf_counter() - t
+        ep_all = a.cpu_sample_epochs * max(1, min(cores, 16)) // 2
+        t = time.perf_counter()
+        upd = oracle.train_hogwild(sp.offsets, sp.indices, M, ep_all, lr, k, seeds["philox"], cores, level=0)
         dt = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": round(upd / dt, 1), "unit": "edge-samples/s", "cores": 1,
+        out["cpu_baseline"] = {"value": round(upd / dt, 1), "unit": "edge-samples/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"FP64 sequential TrainInGPU, {a.cpu_sample_epochs} epochs over the "
-                                         f"level-0 graph ({n0} sources, {upd} updates, {dt:.1f} s)"}
-        log(f"cpu baseline {upd / dt / 1e6:.2f} M edge-samples/s")
+                               "sample": f"FP64 oracle TrainInGPU with each epoch's sources over {cores} OpenMP "
+                                         f"threads (Hogwild), {ep_all} epochs over the level-0 graph ({n0} sources, "
+                                         f"{upd} updates, {dt:.1f} s)",
+                               "single_thread": {"value": round(upd1 / dt1, 1), "cores": 1,
+                                                 "sample": f"sequential oracle, {a.cpu_sample_epochs} epochs "
+                                                           f"({upd1} updates, {dt1:.1f} s)"}}
+        log(f"cpu baseline {upd / dt / 1e6:.2f} M edge-samples/s on {cores} threads, "
+            f"{upd1 / dt1 / 1e6:.2f} M/s on one")
     print(json.dumps(out), flush=True)
+
+
+def scale22_roofline(ctx, d, k, lr, seeds):
+    """Level-0 epoch of a graph whose rows do not fit in the MALL: the
+    scale-22 R-MAT graph (edge factor 16, isolated vertices removed; 2.4M
+    vertices, BF16 rows of 256 B = 0.6 GB), d = 128, k = 3, plain negative
+    stores as in the main workload; 4 untimed epochs, then 8 timed."""
+    import torch
+
+    from paper_2110_10049_amd import gosh as G
+    from synth import init_rows
+    from synth.rmat import drop_isolated_torch, rmat_csr_torch
+
+    off, idx = rmat_csr_torch(22, 16, seeds["graph"], "cuda", offsets_dtype=torch.int32)
+    off, idx, _ = drop_isolated_torch(off, idx)
+    g = G.CSR(off.contiguous(), idx.contiguous())
+    lv = G.gosh_levels_single(ctx, g)
+    n, nnz = lv.shape(0)
+    M = torch.from_numpy(init_rows(n, d, seeds["init"])).cuda().to(torch.bfloat16)
+    G.gosh_train(ctx, lv, 0, M, 4, lr, k)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(ctx.stream)
+    G.gosh_train(ctx, lv, 0, M, 8, lr, k)
+    e.record(ctx.stream)
+    torch.cuda.synchronize()
+    launch_s = s.elapsed_time(e) / 1e3 / 8
+    per_src = 2 * d * 2 * (2 + k) + 2 * 4 + 4
+    ach = n * per_src / launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": "k_train level 0, BF16, d=128, k=3",
+            "graph": f"R-MAT scale 22 ef 16, isolated vertices removed (n={n}, nnz={nnz})",
+            "bytes_per_launch": n * per_src, "launch_us": round(launch_s * 1e6, 2),
+            "cache_served": n * d * 2 <= MALL_BYTES, "rows_bytes": n * d * 2}
 
 
 if __name__ == "__main__":

@@ -82,7 +82,9 @@ gosh_status gosh_ctx_destroy(gosh_ctx* ctx);
  * blocks of asynchronous calls return to the context's cache when the call
  * returns and may be handed out again on the new stream. */
 gosh_status gosh_set_stream(gosh_ctx* ctx, void* hip_stream);
-/* Blocks until all work enqueued by the context has finished. */
+/* Blocks until all work enqueued by the context has finished; returns
+ * GOSH_E_DEVICE if a resident launch's barrier expired since the last call
+ * (see gosh_set_resident_epochs). */
 gosh_status gosh_sync(gosh_ctx* ctx);
 const char* gosh_last_error(const gosh_ctx* ctx);
 /* Bytes currently allocated by the library for this context. */
@@ -129,6 +131,20 @@ gosh_status gosh_set_coarsen_mode(gosh_ctx* ctx, gosh_coarsen_mode mode, int64_t
  * Algorithm 3's barriers everywhere.  Ignored in deterministic mode.
  * epochs_in_flight in [1, 64], min_vertices >= 0. */
 gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int64_t min_vertices);
+
+/* Small levels: gosh_train runs all epochs of a call on a level of at most
+ * `max_vertices` vertices in one cooperative launch, with a device-wide
+ * barrier between epochs instead of a launch boundary (Algorithm 3's epochs
+ * still never overlap; every visit draws the same samples and uses the same
+ * lr and rounding bits as with one launch per epoch).  Levels where negatives
+ * are stored plainly (gosh_set_plain_negatives) keep one launch per epoch.
+ * The barrier's wait is bounded (a few seconds); if one ever expires the
+ * rows are invalid and the next gosh_sync returns GOSH_E_DEVICE.  0 turns it
+ * off; ignored in deterministic mode and with overlapping epochs.  Default:
+ * 0 (off): measured on MI355X, a level's epochs run faster as separate
+ * launches, since after every barrier the rows must be read coherently
+ * across the dies.  max_vertices >= 0. */
+gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices);
 
 /* Write discipline of negative samples (Section 3.1 lets the sources of an
  * epoch race on rows without locks).  By default every row change is applied

@@ -69,6 +69,9 @@ def lib():
                                      C.c_int32, C.c_uint64, C.c_int32, C.c_uint32,
                                      np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")]
         L.orc_train_loss.restype = C.c_int64
+        L.orc_train_hogwild.argtypes = [_i64p, _i32p, C.c_int64, C.POINTER(_Emb), C.c_int32, C.c_double,
+                                        C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32]
+        L.orc_train_hogwild.restype = C.c_int64
         L.orc_draw_all.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32,
                                    C.c_int32, _i32p]
         L.orc_draw_all.restype = None
@@ -228,6 +231,20 @@ def train_loss(offsets, indices, M, epochs, lr, k, seed, level=0, tag=0):
     out = np.zeros(max(epochs, 1), np.float64)
     u = lib().orc_train_loss(offsets, indices, n, C.byref(e), epochs, lr, k, seed, level, tag, out)
     return int(u), out[:epochs]
+
+
+def train_hogwild(offsets, indices, M, epochs, lr, k, seed, threads, level=0, tag=0) -> int:
+    """Algorithm 3 on FP64 rows with each epoch's sources spread over
+    `threads` OpenMP threads without locks (timing of the oracle on all host
+    cores; the rows depend on thread timing).  Returns the executed updates."""
+    offsets, indices = _csr(offsets, indices)
+    n = len(offsets) - 1
+    if M.shape[0] != n or M.dtype != np.float64:
+        raise ValueError("FP64 embedding with one row per vertex")
+    if not 0 <= k <= 15 or threads < 1:
+        raise ValueError("k or threads out of range")
+    e = _emb(M)
+    return int(lib().orc_train_hogwild(offsets, indices, n, C.byref(e), epochs, lr, k, seed, level, tag, threads))
 
 
 # --------------------------------------------------------------------------- coarsening

@@ -1,4 +1,5 @@
-"""Compiles the oracle's C source into oracle/liboracle.so (plain gcc, -O2)."""
+"""Compiles the oracle's C source into oracle/liboracle.so (plain gcc, -O2; OpenMP
+only for the all-core timing variant of the trainer)."""
 from __future__ import annotations
 
 import os
@@ -11,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build() -> str:
     src = os.path.join(HERE, "gosh_oracle.c")
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fno-fast-math",
+    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp",
            "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)

@@ -320,6 +320,29 @@ int64_t orc_train_loss(const int64_t* offsets, const int32_t* indices, int64_t n
     return done;
 }
 
+/* Algorithm 3 as orc_train (FP64 rows, same samples and lr schedule), with
+ * the sources of each epoch spread over `threads` OpenMP threads without
+ * locks (Hogwild, as the paper's parallel loop): rows shared by concurrent
+ * visits race, so the result depends on thread timing.  For timing the
+ * oracle on all host cores; returns the executed updates. */
+int64_t orc_train_hogwild(const int64_t* offsets, const int32_t* indices, int64_t n,
+                          orc_emb* M, int32_t epochs, double lr, int32_t k,
+                          uint64_t seed, int32_t level, uint32_t tag, int32_t threads)
+{
+    int64_t done = 0;
+    for (int32_t j = 0; j < epochs; ++j) {
+        double f = 1.0 - (double)j / (double)epochs;
+        double lrj = lr * (f > 1e-4 ? f : 1e-4);
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1024) reduction(+ : done)
+        for (int64_t src = 0; src < n; ++src) {
+            int32_t samples[64];
+            orc_draw_samples(offsets, indices, n, seed, level, tag, j, src, k, samples);
+            done += orc_visit(M, src, samples, k, lrj, seed, level, tag, j);
+        }
+    }
+    return done;
+}
+
 /* Samples of every source of one epoch (orc_draw_samples for src = 0..n-1):
  * out[src * (1 + k) + t]. */
 void orc_draw_all(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,

@@ -92,6 +92,13 @@ int64_t orc_train_loss(const int64_t* offsets, const int32_t* indices, int64_t n
                        orc_emb* M, int32_t epochs, double lr, int32_t k,
                        uint64_t seed, int32_t level, uint32_t tag, double* loss_out);
 
+/* orc_train over all sources with each epoch's sources spread over `threads`
+ * OpenMP threads without locks (Hogwild; timing only, results depend on
+ * thread timing). */
+int64_t orc_train_hogwild(const int64_t* offsets, const int32_t* indices, int64_t n,
+                          orc_emb* M, int32_t epochs, double lr, int32_t k,
+                          uint64_t seed, int32_t level, uint32_t tag, int32_t threads);
+
 /* orc_draw_samples for every source of one epoch: out[src * (1 + k) + t]. */
 void orc_draw_all(const int64_t* offsets, const int32_t* indices, int64_t n, uint64_t seed,
                   int32_t level, uint32_t tag, int32_t epoch, int32_t k, int32_t* out);

@@ -207,6 +207,14 @@ gosh_status gosh_sync(gosh_ctx* ctx) {
     return guarded(ctx, [&] {
         set_device(&ctx->c);
         GOSH_HIP(hipStreamSynchronize(ctx->c.stream));
+        // a device-wide barrier of a resident launch that waited beyond its limit
+        unsigned int err = 0;
+        char* flag = static_cast<char*>(ctx->c.scratch) + 516;
+        GOSH_HIP(hipMemcpy(&err, flag, 4, hipMemcpyDeviceToHost));
+        if (err) {
+            GOSH_HIP(hipMemset(flag, 0, 4));
+            throw gosh::Error(GOSH_E_DEVICE, "resident epochs: a device-wide barrier waited beyond its spin limit");
+        }
     });
 }
 
@@ -253,6 +261,12 @@ gosh_status gosh_set_coarsen_mode(gosh_ctx* ctx, gosh_coarsen_mode mode, int64_t
 gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices) {
     if (!ctx || min_vertices < 0) return GOSH_E_INVALID_ARG;
     ctx->c.plain_neg_min = min_vertices;
+    return GOSH_OK;
+}
+
+gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices) {
+    if (!ctx || max_vertices < 0) return GOSH_E_INVALID_ARG;
+    ctx->c.resident_max = max_vertices;
     return GOSH_OK;
 }
 

@@ -77,6 +77,72 @@ __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
     }
 }
 
+// Device-wide barrier of a cooperative launch: every block adds one to
+// *count once all its waves arrived, then waits until the count reaches
+// `target` (= blocks x barriers passed).  The wait is bounded: after
+// spin_limit polls the block sets *error and goes on (the results are then
+// invalid, but every wave still exits).
+// The arrival is a release and the poll an acquire at device scope, which
+// make the block's row updates visible to, and the other blocks' updates
+// visible in, the next epoch (the L1 of the block's CU is invalidated by
+// the acquire; __syncthreads orders the block's other waves around it).  The
+// cost grows with the number of arriving blocks (about 1.6 us for 32 blocks
+// against 3-6 us for a kernel launch), so resident launches use few blocks
+// of 16 waves.
+__device__ __forceinline__ void grid_barrier(unsigned int* count, unsigned int target, unsigned int* error,
+                                             unsigned long long spin_limit) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (unsigned long long spins = 0;; ++spins) {
+            if (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (spins >= spin_limit) {
+                atomicOr(error, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int kResBlock = 1024;   // 16 waves per block of a resident launch
+
+// All epochs of a small level in one cooperative launch (Algorithm 3's
+// barrier between epochs kept as a device-wide barrier instead of a launch
+// boundary).  Waves take the level's sources in a grid-stride loop, so every
+// epoch runs exactly the per-epoch launch's visits (same samples, lr and
+// rounding bits); rows written in earlier epochs of the launch are read with
+// coherent loads (kPersistent).  P.e_total epochs; P.loss, when set, has one
+// entry per epoch.
+template <bool BF16, int D, int KMAX, class Off>
+__global__ __launch_bounds__(kResBlock) void k_train_resident(TrainParams P, unsigned int* barrier,
+                                                              unsigned int* error, unsigned long long spin_limit) {
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / L, gl = lane % L;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kResBlock / 64) + (threadIdx.x >> 6);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (kResBlock / 64) * G;
+    for (int j = 0; j < P.e_total; ++j) {
+        TrainParams Q = P;
+        Q.epoch = static_cast<uint32_t>(j);
+        const double f = 1.0 - static_cast<double>(j) / static_cast<double>(P.e_total);
+        Q.lr = static_cast<float>(static_cast<double>(P.lr0) * (f > 1e-4 ? f : 1e-4));
+        Q.loss = P.loss ? P.loss + j : nullptr;
+        for (int64_t base = wave * G; base < P.n; base += stride) {
+            const int64_t slot = base + grp;
+            const float l = visit<BF16, D, KMAX, Off, kPersistent>(Q, slot, slot < P.n, gl);
+            if (Q.loss) wave_add_loss<L>(Q.loss, l, gl);
+        }
+        if (j + 1 < P.e_total) grid_barrier(barrier, static_cast<unsigned int>(j + 1) * gridDim.x, error, spin_limit);
+    }
+}
+
+__global__ void k_zero_word(unsigned int* p) { *p = 0u; }
+
+constexpr int64_t kResidentBlocks = 128;  // blocks of a resident launch at most (fastest in a sweep of 8-256)
+
 template <class Off>
 __global__ void k_draw(TrainParams P, int32_t* out) {
     const int64_t src = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -130,6 +196,40 @@ void launch(const TrainParams& P, int64_t items, hipStream_t st) {
         hipLaunchKernelGGL((k_train<BF16, D, KMAX, Off, MODE>), dim3(static_cast<unsigned>(blocks)),
                            dim3(kBlock), 0, st, P);
     }
+}
+
+// Resident (all epochs in one cooperative launch) kernels.
+struct ResidentKernel {
+    const void* fn;
+    int per_wave;
+};
+
+template <bool BF16, int D, int KMAX>
+ResidentKernel resident_off(bool off64) {
+    return ResidentKernel{off64 ? reinterpret_cast<const void*>(&k_train_resident<BF16, D, KMAX, int64_t>)
+                                : reinterpret_cast<const void*>(&k_train_resident<BF16, D, KMAX, int32_t>),
+                          Lanes<BF16, D>::kG};
+}
+
+template <bool BF16, int D>
+ResidentKernel resident_k(int k, bool off64) {
+    if (k <= 1) return resident_off<BF16, D, 1>(off64);
+    if (k <= 3) return resident_off<BF16, D, 3>(off64);
+    if (k <= 7) return resident_off<BF16, D, 7>(off64);
+    return resident_off<BF16, D, 15>(off64);
+}
+
+template <bool BF16>
+ResidentKernel resident_d(int d, int k, bool off64) {
+    switch (d) {
+        case 8: return resident_k<BF16, 8>(k, off64);
+        case 16: return resident_k<BF16, 16>(k, off64);
+        case 32: return resident_k<BF16, 32>(k, off64);
+        case 64: return resident_k<BF16, 64>(k, off64);
+        case 128: return resident_k<BF16, 128>(k, off64);
+        case 256: return resident_k<BF16, 256>(k, off64);
+    }
+    return ResidentKernel{nullptr, 0};
 }
 
 template <bool BF16, int D, int KMAX, int MODE>
@@ -235,6 +335,27 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     }
     GOSH_REQUIRE(!c->loss || c->loss_cap >= epochs, GOSH_E_INVALID_ARG,
                  "loss record buffer holds fewer entries than the call's epochs");
+    if (!c->deterministic && span == 1 && epochs > 1 && L.n <= c->resident_max && P.plain_neg == 0) {
+        // all epochs in one cooperative launch with device-wide barriers
+        const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64) : resident_d<false>(d, k, L.off64);
+        GOSH_REQUIRE(R.fn, GOSH_E_INVALID_ARG, "unsupported training shape");
+        int per_cu = 0, cus = 0;
+        GOSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, R.fn, kResBlock, 0));
+        GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        const int64_t need = ceil_div(L.n, static_cast<int64_t>(kResBlock / 64) * R.per_wave);
+        const int64_t cap = std::min<int64_t>(static_cast<int64_t>(std::max(per_cu, 1)) * cus, kResidentBlocks);
+        const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min(need, cap)));
+        unsigned int* bar = reinterpret_cast<unsigned int*>(static_cast<char*>(c->scratch) + 512);
+        unsigned int* err = reinterpret_cast<unsigned int*>(static_cast<char*>(c->scratch) + 516);
+        hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, c->stream, bar);
+        GOSH_HIP(hipGetLastError());
+        P.lr = lr;
+        P.epoch = 0;
+        P.loss = c->loss;
+        unsigned long long spin_limit = 1ull << 22;   // a few seconds of polling
+        void* args[] = {&P, &bar, &err, &spin_limit};
+        GOSH_HIP(hipLaunchCooperativeKernel(R.fn, dim3(blocks), dim3(kResBlock), args, 0, c->stream));
+    } else {
     for (int j = 0; j < epochs; j += span) {
         const double f = 1.0 - static_cast<double>(j) / static_cast<double>(epochs);
         P.lr = static_cast<float>(static_cast<double>(lr) * (f > 1e-4 ? f : 1e-4));
@@ -243,6 +364,7 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
         P.loss = c->loss ? c->loss + j : nullptr;
         fn(P, L.n * P.span, c->stream);
         GOSH_HIP(hipGetLastError());
+    }
     }
     if (updates_dev) {
         const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(L.n, 256), 1024));

@@ -34,6 +34,11 @@ class EmbedConfig:
     sampler: str = "edge"
     walk_len: int = 10
     window: int = 3
+    # epoch unit of the schedule: "passes" (one epoch = one pass of
+    # Algorithm 3, every vertex a source once) or "edges" (the unit of the
+    # paper's experiments, one epoch = |E| updates: level i's share e_i
+    # becomes e_i * ceil(nnz_i / (2 n_i)) passes)
+    epoch_unit: str = "passes"
 
 
 @dataclass
@@ -46,11 +51,25 @@ class EmbedResult:
     timings: dict = field(default_factory=dict)
     # trained rows of every level (level -> tensor), when asked for with keep_levels
     trained: dict = field(default_factory=dict)
+    # executed UpdateEmbed calls of each level (level -> int64 device tensor)
+    level_updates: dict = field(default_factory=dict)
+    # running loss of every epoch of each level (level -> float64 device tensor), with record_loss
+    losses: dict = field(default_factory=dict)
+
+
+def unit_epochs(sched, shapes, unit):
+    """Epochs of each level in Algorithm 3 passes (see EmbedConfig.epoch_unit);
+    shapes[i] = (n_i, nnz_i)."""
+    if unit == "passes":
+        return list(sched)
+    if unit != "edges":
+        raise ValueError(f"unknown epoch unit {unit!r}")
+    return [int(e) * (max(1, -(-nnz // (2 * n))) if n > 0 else 1) for e, (n, nnz) in zip(sched, shapes)]
 
 
 def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels | None = None,
           coarsen: bool = True, level_events: bool = False, mlp: G.Mlp | None = None,
-          keep_levels: bool = False) -> EmbedResult:
+          keep_levels: bool = False, record_loss: bool = False) -> EmbedResult:
     """init_fn(n, d) -> device tensor [n, d] of cfg.dtype for the coarsest level.
 
     With level_events, timings["train_events"][i] holds a (start, end) pair
@@ -59,23 +78,35 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
     level 0's sampling and update launches (the call waits for level 0).
     mlp: expand with the learned prolongation instead of the copy.
     keep_levels: keep every level's trained rows in result.trained (the
-    (coarse, fine) pairs the prolongation network is trained on)."""
+    (coarse, fine) pairs the prolongation network is trained on).
+    record_loss: record every epoch's running loss of the per-epoch trainer
+    (result.losses).  With level_events, timings["coarsen_events"] holds
+    events around the coarsening."""
     if cfg.sampler not in ("edge", "walk"):
         raise ValueError(f"unknown sampler {cfg.sampler!r}")
+    ev_c = None
     if levels is None:
+        if level_events:
+            ev_c = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev_c[0].record(ctx.stream)
         levels = G.gosh_coarsen(ctx, g0, cfg.threshold, cfg.max_ratio) if coarsen else G.gosh_levels_single(ctx, g0)
+        if level_events:
+            ev_c[1].record(ctx.stream)
     D = levels.count()
     sizes = levels.sizes()
-    sched = G.gosh_epoch_schedule(cfg.epochs, cfg.p, D)
+    shapes = [levels.shape(i) for i in range(D)]
+    sched = unit_epochs(G.gosh_epoch_schedule(cfg.epochs, cfg.p, D), shapes, cfg.epoch_unit)
     dev = f"cuda:{ctx.device}"
     M = init_fn(sizes[-1], cfg.d)
     if M.dtype != cfg.dtype or tuple(M.shape) != (sizes[-1], cfg.d):
         raise ValueError("init_fn returned a wrong shape or dtype")
-    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    counters = torch.zeros(D, dtype=torch.int64, device=dev)
     events = {}
     events_walk = None
     trained = {}
+    losses = {}
     for i in range(D - 1, -1, -1):
+        counter = counters[i:i + 1]
         if level_events:
             ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             ev[0].record(ctx.stream)
@@ -87,6 +118,13 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
         elif cfg.batch_levels_upto and sizes[i] <= cfg.batch_levels_upto:
             G.gosh_train_batched(ctx, [(levels.csr(i), M, sched[i], cfg.lr, i, cfg.tag)], cfg.k,
                                  cfg.batch_mode, updates=counter)
+        elif record_loss:
+            losses[i] = torch.zeros(max(sched[i], 1), dtype=torch.float64, device=dev)
+            ctx.set_loss_record(losses[i])
+            try:
+                G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
+            finally:
+                ctx.set_loss_record(None)
         else:
             G.gosh_train(ctx, levels, i, M, sched[i], cfg.lr, cfg.k, cfg.tag, counter)
         if level_events:
@@ -98,5 +136,6 @@ def embed(ctx: G.Context, g0: G.CSR, cfg: EmbedConfig, init_fn, levels: G.Levels
             fine = torch.empty((sizes[i - 1], cfg.d), dtype=cfg.dtype, device=dev)
             G.gosh_prolong(ctx, levels, i - 1, M, fine, mlp=mlp)
             M = fine
-    return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counter, levels=levels,
-                       timings={"train_events": events, "walk_level0": events_walk}, trained=trained)
+    return EmbedResult(emb=M, sizes=sizes, schedule=sched, updates=counters.sum().reshape(1), levels=levels,
+                       timings={"train_events": events, "walk_level0": events_walk, "coarsen_events": ev_c},
+                       trained=trained, level_updates={i: counters[i] for i in range(D)}, losses=losses)

@@ -85,6 +85,7 @@ _SIGNATURES = [
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
     ("gosh_set_loss_record", C.c_int, [_P, _P, C.c_int64]),
+    ("gosh_set_resident_epochs", C.c_int, [_P, C.c_int64]),
     ("gosh_set_draw_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_trim", C.c_int, [_P]),
     ("gosh_set_coarsen_mode", C.c_int, [_P, C.c_int, C.c_int64]),
@@ -221,6 +222,10 @@ class Context:
     def set_plain_negatives(self, min_vertices: int):
         """Plain stores for negative rows on levels of at least min_vertices vertices (0 = off)."""
         self.check(self._L.gosh_set_plain_negatives(self.h, min_vertices))
+
+    def set_resident_epochs(self, max_vertices: int):
+        """All epochs of a level of at most max_vertices vertices in one launch (0 = off)."""
+        self.check(self._L.gosh_set_resident_epochs(self.h, max_vertices))
 
     def set_loss_record(self, loss: "torch.Tensor | None"):
         """Running loss per epoch of later gosh_train calls, added to a float64

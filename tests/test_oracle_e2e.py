@@ -45,3 +45,23 @@ def test_driver_order_and_prolongation(orc):
     for c in range(0, int(mp0.max()) + 1, 37):
         rows = M[mp0 == c]
         assert np.all(rows == rows[0])
+
+
+def test_edge_epoch_unit(orc):
+    # one epoch = |E| updates (the note under Table 3): a pass of Algorithm 3
+    # makes n positive updates, so level i needs ceil(nnz_i / (2 n_i)) passes
+    # per epoch; at least one, also for an edgeless level
+    from paper_2110_10049_amd.driver import unit_epochs
+    graphs = [(np.array([0, 3, 5, 8, 10]), None),      # n = 4, nnz = 10 -> ceil(10 / 8) = 2
+              (np.array([0, 0, 0, 0]), None),          # n = 3, edgeless -> 1
+              (np.array([0, 2, 4]), None),             # n = 2, nnz = 4 -> 1
+              (np.array([0, 6, 12, 18, 24]), None)]    # n = 4, nnz = 24 (K_4 has 12) -> 3
+    sched = [10, 11, 12, 13]
+    want = [20, 11, 12, 39]
+    assert list(orc.unit_epochs(sched, graphs, "edges")) == want
+    assert list(orc.unit_epochs(sched, graphs, "passes")) == sched
+    shapes = [(len(o) - 1, int(o[-1])) for o, _ in graphs]
+    assert unit_epochs(sched, shapes, "edges") == want
+    assert unit_epochs(sched, shapes, "passes") == sched
+    with pytest.raises(ValueError):
+        unit_epochs(sched, shapes, "vertices")

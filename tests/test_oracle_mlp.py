@@ -89,6 +89,42 @@ def test_adam_first_step_is_signed_lr():
         assert np.allclose(step[big], 1e-3 * np.sign(G[big]), rtol=1e-3)
 
 
+def test_adam_constant_gradient_steps_are_signed_lr():
+    # under a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    # of the first five steps moves a weight by lr * g / (|g| + eps); a wrong
+    # bias-correction exponent changes every step from the second on
+    P = mlp.Params(np.zeros((2, 3)), np.zeros(2), np.zeros((3, 2)), np.zeros(3))
+    g = mlp.Params(np.array([[0.3, -2.0, 1e-3], [5.0, -0.25, 0.7]]), np.array([1.0, -1.0]),
+                   np.full((3, 2), -0.125), np.array([0.5, 3.0, -7.0]))
+    S = mlp.adam_init(P)
+    lr, eps = 1e-2, 1e-8
+    for t in range(1, 6):
+        before = P.copy()
+        mlp.adam_step(P, g, S, lr)
+        for name in ("W1", "b1", "W2", "b2"):
+            G = getattr(g, name)
+            step = getattr(before, name) - getattr(P, name)
+            assert np.allclose(step, lr * G / (np.abs(G) + eps), rtol=1e-9, atol=0), (t, name)
+
+
+def test_adam_two_gradients_by_hand():
+    # one weight, gradients 1 then -0.5, lr 0.1, beta 0.9 / 0.999, eps 1e-8:
+    #   t=1: m = 0.1, v = 0.001, m^ = 1, v^ = 1       -> step 0.1 / (1 + 1e-8)
+    #   t=2: m = 0.09 - 0.05 = 0.04, v = 0.000999 + 0.00025 = 0.001249,
+    #        m^ = 0.04 / 0.19, v^ = 0.001249 / 0.001999
+    P = mlp.Params(np.zeros((1, 1)), np.zeros(1), np.zeros((1, 1)), np.zeros(1))
+    S = mlp.adam_init(P)
+    one = lambda x: mlp.Params(np.full((1, 1), x), np.zeros(1), np.zeros((1, 1)), np.zeros(1))
+    mlp.adam_step(P, one(1.0), S, 0.1)
+    w1 = -0.1 / (1.0 + 1e-8)
+    assert P.W1[0, 0] == pytest.approx(w1, rel=1e-14)
+    mlp.adam_step(P, one(-0.5), S, 0.1)
+    step2 = 0.1 * (0.04 / 0.19) / (math.sqrt(0.001249 / 0.001999) + 1e-8)
+    assert P.W1[0, 0] == pytest.approx(w1 - step2, rel=1e-12)
+    assert P.W1[0, 0] == pytest.approx(-0.1 - 0.02663370, abs=1e-7)   # 0.2105263 / 0.7904508 * 0.1
+
+
 def test_training_reduces_mse():
     rng = np.random.default_rng(4)
     B, d, H = 256, 8, 16

@@ -219,3 +219,20 @@ def test_train_lr_schedule_and_determinism(orc):
     assert np.array_equal(A, C)
     deg0 = int((np.diff(off) == 0).sum())
     assert ua <= 3 * n * 3 and ua >= 3 * (n - deg0)
+
+
+def test_hogwild_trainer_one_thread_is_sequential(orc):
+    # the all-core timing variant with one thread is orc.train exactly; with
+    # several threads it executes the same number of updates
+    from synth import init_rows, rmat_csr
+    off, idx = rmat_csr(10, 8, seed=5)
+    n = len(off) - 1
+    A = init_rows(n, 16, 3).astype(np.float64)
+    B = A.copy()
+    C = A.copy()
+    u1 = orc.train(off, idx, A, 3, 0.05, 2, 4, level=1, tag=3)
+    u2 = orc.train_hogwild(off, idx, B, 3, 0.05, 2, 4, 1, level=1, tag=3)
+    u3 = orc.train_hogwild(off, idx, C, 3, 0.05, 2, 4, 4, level=1, tag=3)
+    assert u1 == u2 == u3
+    assert np.array_equal(A, B)
+    assert np.all(np.isfinite(C)) and np.abs(C - A).max() < 0.05
