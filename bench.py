@@ -114,6 +114,9 @@ def parse():
                          "everywhere)")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-loss", action="store_true", help="skip the untimed running-loss passes")
+    ap.add_argument("--lds-levels", type=int, default=0,
+                    help="train levels / batched jobs of at most this many vertices whose rows fit in LDS inside "
+                         "one workgroup (0: off)")
     ap.add_argument("--no-big-roofline", action="store_true", help="skip the scale-22 level-0 roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -145,6 +148,7 @@ def batch_workload(a):
     ns = np.floor(2 ** rng.uniform(10, 16, size=512)).astype(np.int64)
     efs = rng.uniform(4, 32, size=512)
     ctx = G.Context(0, seed=4)
+    ctx.set_lds_levels(a.lds_levels)
     graphs, epochs, levels = [], [], []
     for j in range(512):
         n = int(ns[j])
@@ -201,7 +205,7 @@ def batch_workload(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "512 R-MAT graphs (|V| log-uniform 1k-64k, edge factor U(4,32)) + "
                                f"{coarse} coarse levels (<=100k vertices) of R-MAT scale 22, d=64, k=3, BF16",
-                   "jobs": len(jobs), "sources_per_step": sources // a.steps,
+                   "jobs": len(jobs), "sources_per_step": sources // a.steps, "lds_levels": a.lds_levels,
                    "execution": {"mode": ["auto", "persistent", "epoch_graph"][chosen[0]],
                                  "blocks_per_cu": chosen[1], "chunk_iterations": chosen[2]}},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -731,6 +735,7 @@ def main_workload(a):
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     ctx.set_plain_negatives(a.plain_neg_min)
     ctx.set_coarsen_mode(G.GOSH_COARSEN_LOCK_SKIP if a.coarsen == "lock-skip" else G.GOSH_COARSEN_EXACT)
+    ctx.set_lds_levels(a.lds_levels)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
 

@@ -146,6 +146,28 @@ gosh_status gosh_set_epoch_overlap(gosh_ctx* ctx, int32_t epochs_in_flight, int6
  * across the dies.  max_vertices >= 0. */
 gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices);
 
+/* Hot coarse levels in LDS: gosh_train trains a level of at most
+ * `max_vertices` vertices whose rows and one epoch's samples fit in the
+ * 160 KiB LDS of one compute unit (n d b + 4 n (1 + k) bytes, b = 4 for
+ * FP32, 2 for BF16) inside a single workgroup of 16 waves: the rows are read
+ * from HBM once, every epoch draws the samples of all sources into an LDS
+ * table (the same Philox draws as the per-epoch launch) and then visits the
+ * sources with the rows in LDS, a workgroup barrier between epochs (Section
+ * 3.1's shared-memory staging applied to the whole level), and the rows are
+ * written back once.  The sources of an epoch run concurrently over the 16
+ * waves; BF16 words are committed by LDS compare-and-swap (exactly the
+ * stochastically rounded pair when uncontended, the change added to the
+ * current value and rounded again otherwise).  Levels where negatives are
+ * stored plainly keep one launch per epoch; ignored in deterministic mode
+ * and with overlapping epochs.  gosh_train_batched applies the same to every
+ * job of at most max_vertices vertices that fits: such jobs run first, one
+ * workgroup each in one launch, the others as before (not
+ * gosh_train_batched_noalloc).  Default 0 (off): measured on MI355X, one
+ * launch per epoch over the whole device is faster for single levels (a
+ * workgroup serialises an epoch into rounds of 64 visits).
+ * max_vertices >= 0. */
+gosh_status gosh_set_lds_levels(gosh_ctx* ctx, int64_t max_vertices);
+
 /* Write discipline of negative samples (Section 3.1 lets the sources of an
  * epoch race on rows without locks).  By default every row change is applied
  * with atomic adds, so no concurrent update is lost.  With min_vertices > 0,

@@ -270,6 +270,12 @@ gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices) {
     return GOSH_OK;
 }
 
+gosh_status gosh_set_lds_levels(gosh_ctx* ctx, int64_t max_vertices) {
+    if (!ctx || max_vertices < 0) return GOSH_E_INVALID_ARG;
+    ctx->c.lds_max = max_vertices;
+    return GOSH_OK;
+}
+
 gosh_status gosh_set_draw_record(gosh_ctx* ctx, int32_t* samples_dev, int64_t capacity) {
     if (!ctx || capacity < 0 || (samples_dev && capacity == 0)) return GOSH_E_INVALID_ARG;
     ctx->c.record = samples_dev;

@@ -199,6 +199,21 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiArgs A) {
     visit_job<BF16, D, KMAX, kEpoch>(J, P, slot - A.job_src0[j], true, gl);
 }
 
+// Jobs whose rows fit in LDS, one workgroup each: every epoch of job
+// blockIdx.x inside the workgroup (train_rows_in_lds), rows read from HBM
+// once and written back once.
+template <bool BF16, int D, int KMAX>
+__global__ __launch_bounds__(kLdsBlock) void k_batched_lds(const BJob* jobs, int k, uint32_t key0, uint32_t key1,
+                                                           unsigned long long* updates) {
+    extern __shared__ __align__(16) unsigned char lds_rows[];
+    const BJob J = jobs[blockIdx.x];
+    TrainParams P = job_params(J, 0, k, key0, key1, updates);
+    P.e_total = J.epochs;
+    P.lr0 = J.lr;
+    if (J.off64) train_rows_in_lds<BF16, D, KMAX, int64_t>(P, lds_rows);
+    else train_rows_in_lds<BF16, D, KMAX, int32_t>(P, lds_rows);
+}
+
 // Clears `n` 64-bit words (a kernel rather than a memset node, so that the
 // call stays valid inside a captured stream).
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
@@ -235,12 +250,14 @@ struct Kernels {
     const void* persist;
     const void* multi;
     int per_wave;      // sources per wave
+    const void* lds;
 };
 
 template <bool BF16, int D, int KMAX>
 Kernels kernels_for() {
     return Kernels{reinterpret_cast<const void*>(&k_persist<BF16, D, KMAX>),
-                   reinterpret_cast<const void*>(&k_multi<BF16, D, KMAX>), Lanes<BF16, D>::kG};
+                   reinterpret_cast<const void*>(&k_multi<BF16, D, KMAX>), Lanes<BF16, D>::kG,
+                   reinterpret_cast<const void*>(&k_batched_lds<BF16, D, KMAX>)};
 }
 
 template <bool BF16, int D>
@@ -261,7 +278,7 @@ Kernels pick_d(int d, int k) {
         case 128: return pick_k<BF16, 128>(k);
         case 256: return pick_k<BF16, 256>(k);
     }
-    return Kernels{nullptr, nullptr, 0};
+    return Kernels{nullptr, nullptr, 0, nullptr};
 }
 
 
@@ -682,6 +699,49 @@ void train_batched(Ctx* c, const gosh_job* jobs, int njobs, gosh_dtype dt, int d
     if (chosen) chosen[0] = chosen[1] = chosen[2] = 0;
     if (kept.empty()) return;
     const Kernels K = dt == GOSH_BF16 ? pick_d<true>(d, k) : pick_d<false>(d, k);
+    if (!c->deterministic && c->lds_max > 0) {
+        // jobs whose rows fit in one workgroup's LDS: one workgroup each
+        std::vector<BJob> lj;
+        std::vector<gosh_job> rest;
+        int64_t bytes = 0;
+        for (const auto& q : kept) {
+            const int64_t b = lds_level_bytes(q.g.n, d, dt == GOSH_BF16 ? 2 : 4, k);
+            if (q.g.n <= c->lds_max && b <= 160 * 1024) {
+                BJob J{};
+                J.offsets = q.g.offsets;
+                J.indices = q.g.indices;
+                J.emb = q.emb;
+                J.n = q.g.n;
+                J.nnz = q.g.nnz;
+                J.lr = q.lr;
+                J.epochs = q.epochs;
+                J.w2 = stream_word2(q.level, q.tag);
+                J.off64 = q.g.offsets_is_i64 ? 1 : 0;
+                lj.push_back(J);
+                bytes = std::max(bytes, b);
+            } else {
+                rest.push_back(q);
+            }
+        }
+        if (!lj.empty()) {
+            DevBuf<BJob> dj(c, lj.size());
+            GOSH_HIP(hipMemcpyAsync(dj.p, lj.data(), sizeof(BJob) * lj.size(), hipMemcpyHostToDevice, c->stream));
+            GOSH_HIP(hipFuncSetAttribute(K.lds, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)));
+            auto* upd = reinterpret_cast<unsigned long long*>(updates_dev);
+            const uint32_t key0 = static_cast<uint32_t>(c->seed), key1 = static_cast<uint32_t>(c->seed >> 32);
+            const BJob* jp = dj.p;
+            void* args[] = {&jp, &k, const_cast<uint32_t*>(&key0), const_cast<uint32_t*>(&key1), &upd};
+            GOSH_HIP(hipLaunchKernel(K.lds, dim3(static_cast<unsigned>(lj.size())), dim3(kLdsBlock), args,
+                                     static_cast<size_t>(bytes), c->stream));
+            if (upd) {
+                hipLaunchKernelGGL(k_add_job_updates, dim3(static_cast<unsigned>(lj.size())), dim3(256), 0,
+                                   c->stream, dj.p, k, upd);
+                GOSH_HIP(hipGetLastError());
+            }
+        }
+        kept.swap(rest);
+        if (kept.empty()) return;
+    }
     Plan P;
     build_plan(c, kept.data(), static_cast<int>(kept.size()), P);
     RunShape R{GOSH_BATCH_PERSISTENT, 2, 4};

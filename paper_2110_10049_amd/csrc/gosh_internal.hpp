@@ -46,6 +46,7 @@ struct Ctx {
     int64_t overlap_min = 0;   // levels with at least this many vertices overlap
     int64_t plain_neg_min = 0; // levels with at least this many vertices store negatives plainly (0: never)
     int64_t resident_max = 0;  // levels with at most this many vertices run all epochs in one launch (0: never)
+    int64_t lds_max = 0;       // levels with at most this many vertices (and rows fitting in LDS) train in one workgroup
     int32_t* record = nullptr; // test hook: samples drawn inside gosh_train (device, caller-owned)
     int64_t record_cap = 0;
     double* loss = nullptr;    // running loss per epoch of gosh_train (device, caller-owned)

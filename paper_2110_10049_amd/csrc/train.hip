@@ -139,6 +139,16 @@ __global__ __launch_bounds__(kResBlock) void k_train_resident(TrainParams P, uns
     }
 }
 
+// A level whose rows fit in one workgroup's LDS: all epochs inside one
+// workgroup (train_rows_in_lds); dynamic LDS = lds_level_bytes.
+template <bool BF16, int D, int KMAX, class Off>
+__global__ __launch_bounds__(kLdsBlock) void k_train_lds(TrainParams P) {
+    extern __shared__ __align__(16) unsigned char lds_rows[];
+    train_rows_in_lds<BF16, D, KMAX, Off>(P, lds_rows);
+}
+
+constexpr int64_t kLdsMaxBytes = 160 * 1024;   // LDS of one CU
+
 __global__ void k_zero_word(unsigned int* p) { *p = 0u; }
 
 constexpr int64_t kResidentBlocks = 128;  // blocks of a resident launch at most (fastest in a sweep of 8-256)
@@ -205,29 +215,33 @@ struct ResidentKernel {
 };
 
 template <bool BF16, int D, int KMAX>
-ResidentKernel resident_off(bool off64) {
+ResidentKernel resident_off(bool off64, bool lds) {
+    if (lds)
+        return ResidentKernel{off64 ? reinterpret_cast<const void*>(&k_train_lds<BF16, D, KMAX, int64_t>)
+                                    : reinterpret_cast<const void*>(&k_train_lds<BF16, D, KMAX, int32_t>),
+                              Lanes<BF16, D>::kG};
     return ResidentKernel{off64 ? reinterpret_cast<const void*>(&k_train_resident<BF16, D, KMAX, int64_t>)
                                 : reinterpret_cast<const void*>(&k_train_resident<BF16, D, KMAX, int32_t>),
                           Lanes<BF16, D>::kG};
 }
 
 template <bool BF16, int D>
-ResidentKernel resident_k(int k, bool off64) {
-    if (k <= 1) return resident_off<BF16, D, 1>(off64);
-    if (k <= 3) return resident_off<BF16, D, 3>(off64);
-    if (k <= 7) return resident_off<BF16, D, 7>(off64);
-    return resident_off<BF16, D, 15>(off64);
+ResidentKernel resident_k(int k, bool off64, bool lds) {
+    if (k <= 1) return resident_off<BF16, D, 1>(off64, lds);
+    if (k <= 3) return resident_off<BF16, D, 3>(off64, lds);
+    if (k <= 7) return resident_off<BF16, D, 7>(off64, lds);
+    return resident_off<BF16, D, 15>(off64, lds);
 }
 
 template <bool BF16>
-ResidentKernel resident_d(int d, int k, bool off64) {
+ResidentKernel resident_d(int d, int k, bool off64, bool lds = false) {
     switch (d) {
-        case 8: return resident_k<BF16, 8>(k, off64);
-        case 16: return resident_k<BF16, 16>(k, off64);
-        case 32: return resident_k<BF16, 32>(k, off64);
-        case 64: return resident_k<BF16, 64>(k, off64);
-        case 128: return resident_k<BF16, 128>(k, off64);
-        case 256: return resident_k<BF16, 256>(k, off64);
+        case 8: return resident_k<BF16, 8>(k, off64, lds);
+        case 16: return resident_k<BF16, 16>(k, off64, lds);
+        case 32: return resident_k<BF16, 32>(k, off64, lds);
+        case 64: return resident_k<BF16, 64>(k, off64, lds);
+        case 128: return resident_k<BF16, 128>(k, off64, lds);
+        case 256: return resident_k<BF16, 256>(k, off64, lds);
     }
     return ResidentKernel{nullptr, 0};
 }
@@ -335,7 +349,19 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     }
     GOSH_REQUIRE(!c->loss || c->loss_cap >= epochs, GOSH_E_INVALID_ARG,
                  "loss record buffer holds fewer entries than the call's epochs");
-    if (!c->deterministic && span == 1 && epochs > 1 && L.n <= c->resident_max && P.plain_neg == 0) {
+    const int64_t lds_bytes = lds_level_bytes(L.n, d, dt == GOSH_BF16 ? 2 : 4, k);
+    if (!c->deterministic && span == 1 && P.plain_neg == 0 && L.n <= c->lds_max && lds_bytes <= kLdsMaxBytes) {
+        // the level's rows and one epoch's samples in one workgroup's LDS
+        const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64, true)
+                                                 : resident_d<false>(d, k, L.off64, true);
+        GOSH_REQUIRE(R.fn, GOSH_E_INVALID_ARG, "unsupported training shape");
+        GOSH_HIP(hipFuncSetAttribute(R.fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)));
+        P.lr = lr;
+        P.epoch = 0;
+        P.loss = c->loss;
+        void* args[] = {&P};
+        GOSH_HIP(hipLaunchKernel(R.fn, dim3(1), dim3(kLdsBlock), args, static_cast<size_t>(lds_bytes), c->stream));
+    } else if (!c->deterministic && span == 1 && epochs > 1 && L.n <= c->resident_max && P.plain_neg == 0) {
         // all epochs in one cooperative launch with device-wide barriers
         const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64) : resident_d<false>(d, k, L.off64);
         GOSH_REQUIRE(R.fn, GOSH_E_INVALID_ARG, "unsupported training shape");

@@ -42,7 +42,7 @@ struct TrainParams {
     double* loss;             // optional: running loss per epoch of the launch (index = epoch - first)
 };
 
-enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3 };
+enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3, kLds = 4 };
 
 // Lane layout of a d-wide row.  A group of L lanes serves one row; lane gl
 // owns the 32-bit words gl + L*i, i < WPL (FP32: one element per word, BF16:
@@ -200,6 +200,88 @@ struct RowIO<true> {
     }
 };
 
+// Rows held in one workgroup's LDS (a level or job trained inside a single
+// workgroup): the same interface as RowIO, with the workgroup as the only
+// writer.  FP32 changes are LDS atomic adds; a BF16 word is committed by
+// compare-and-swap: uncontended it becomes exactly the stochastically
+// rounded pair, and a half that another wave changed in the meantime gets
+// this visit's change v - cur added to its current value and rounded again
+// with the same bits (LDS swaps take a few cycles, so the loop is cheap).
+template <bool BF16>
+struct LdsRowIO;
+
+template <>
+struct LdsRowIO<false> {
+    using Elem = float;
+    template <int D, bool COH>
+    __device__ static void load(const float* M, int64_t row, int gl, float (&x)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        const float* p = M + row * D + gl;
+#pragma unroll
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i) x[i] = p[L * i];
+    }
+    template <int D>
+    __device__ static void store(float* M, int64_t row, int gl, const float (&x)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        float* p = M + row * D + gl;
+#pragma unroll
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i) p[L * i] = x[i];
+    }
+    template <int D>
+    __device__ static void add(float* M, int64_t row, int gl, const float (&dx)[Lanes<false, D>::kEPL]) {
+        constexpr int L = Lanes<false, D>::kL;
+        float* p = M + row * D + gl;
+#pragma unroll
+        for (int i = 0; i < Lanes<false, D>::kWPL; ++i)
+            __hip_atomic_fetch_add(p + L * i, dx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
+
+template <>
+struct LdsRowIO<true> {
+    using Elem = uint16_t;
+    template <int D, bool COH>
+    __device__ static void load(const uint16_t* M, int64_t row, int gl, uint32_t (&w)[Lanes<true, D>::kWPL]) {
+        constexpr int L = Lanes<true, D>::kL;
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(M + row * D) + gl;
+#pragma unroll
+        for (int i = 0; i < Lanes<true, D>::kWPL; ++i) w[i] = p[L * i];
+    }
+    template <int D, bool PLAIN = false>
+    __device__ static void commit(uint16_t* M, int64_t row, int gl, const uint32_t (&cur)[Lanes<true, D>::kWPL],
+                                  const float (&v)[Lanes<true, D>::kEPL], uint4 r,
+                                  uint32_t (&out)[Lanes<true, D>::kWPL]) {
+        using Ly = Lanes<true, D>;
+        constexpr int L = Ly::kL;
+        uint32_t* p = reinterpret_cast<uint32_t*>(M + row * D) + gl;
+        const int q0 = gl / Ly::kBlocks;
+#pragma unroll
+        for (int i = 0; i < Ly::kWPL; ++i) {
+            const int q = q0 + i * (L / Ly::kBlocks);
+            const uint32_t bits = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+            const uint32_t t0 = bf16_sr(v[2 * i], bits & 0xFFFFu) & 0xFFFFu;
+            const uint32_t t1 = bf16_sr(v[2 * i + 1], bits >> 16) & 0xFFFFu;
+            const uint32_t want = t0 | (t1 << 16);
+            out[i] = want;
+            uint32_t expected = cur[i];
+            uint32_t desired = want;
+            // bounded: a word changes at most once per other visit in flight
+            for (int it = 0; it < 1024; ++it) {
+                if (__hip_atomic_compare_exchange_strong(p + L * i, &expected, desired, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                const uint32_t h0 = expected & 0xFFFFu, h1 = expected >> 16;
+                const uint32_t s0 = cur[i] & 0xFFFFu, s1 = cur[i] >> 16;
+                const uint32_t n0 = h0 == s0 ? t0
+                                             : bf16_sr(bf16_lo(h0) + (v[2 * i] - bf16_lo(s0)), bits & 0xFFFFu) & 0xFFFFu;
+                const uint32_t n1 = h1 == s1 ? t1
+                                             : bf16_sr(bf16_lo(h1) + (v[2 * i + 1] - bf16_lo(s1)), bits >> 16) & 0xFFFFu;
+                desired = n0 | (n1 << 16);
+            }
+        }
+    }
+};
+
 __device__ __forceinline__ float sigmoidf_(float x) {
     return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
 }
@@ -222,7 +304,7 @@ __device__ __forceinline__ float softplusf_(float z) {
 // the same launch).  Returns, when want_loss, the visit's running loss: the
 // Section 2 objective of each executed update at the dot it reads (the same
 // value on every lane of the group); 0 otherwise.
-template <bool BF16, int D, int KMAX, bool COH>
+template <bool BF16, int D, int KMAX, bool COH, class IO = RowIO<BF16>>
 __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, int64_t src,
                                               typename RowIO<BF16>::Elem* Mo, int64_t self,
                                               const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
@@ -233,7 +315,6 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
     constexpr int L = Ly::kL;
     constexpr int E = Ly::kEPL;
     constexpr int W = Ly::kWPL;
-    using IO = RowIO<BF16>;
     const uint32_t blk = (blk_hi << 8) | static_cast<uint32_t>(gl % Ly::kBlocks);
     int done = 0;
     float lsum = 0.0f;
@@ -373,7 +454,7 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
 // Returns the visit's running loss when P.loss is set (see update_chain), 0
 // for an inactive slot.  With P.record set, the drawn samples are written to
 // record[src * (1 + k) + t].
-template <bool BF16, int D, int KMAX, class Off, int MODE>
+template <bool BF16, int D, int KMAX, class Off, int MODE, class IO = RowIO<BF16>>
 __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool active, int gl) {
     using Elem = typename RowIO<BF16>::Elem;
     Elem* M = static_cast<Elem*>(P.emb);
@@ -384,7 +465,14 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) u[t] = -1;
 
-    if constexpr (MODE == kExplicit) {
+    if constexpr (MODE == kLds) {
+        // the epoch's samples were drawn into the table P.samples beforehand
+        if (active) {
+#pragma unroll
+            for (int t = 0; t <= KMAX; ++t)
+                if (t <= k) u[t] = P.samples[slot * (1 + k) + t];
+        }
+    } else if constexpr (MODE == kExplicit) {
         if (active) {
             src = P.src_list[slot];
             active = src >= 0 && src < P.n_rows;
@@ -432,9 +520,39 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
         }
     }
     if (!active) return 0.0f;
-    return update_chain<BF16, D, KMAX, MODE == kPersistent>(
+    return update_chain<BF16, D, KMAX, MODE == kPersistent, IO>(
         M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates,
         gl, (MODE == kEpoch || MODE == kExplicit) && P.plain_neg != 0, P.loss != nullptr);
+}
+
+// Samples of source `src` in epoch P.epoch (kind 0 of the Philox stream), as
+// the per-epoch kernel draws them: out[0] the positive (-1 without
+// neighbours), out[t] negative t.
+template <class Off>
+__device__ __forceinline__ void draw_source(const TrainParams& P, int64_t src, int32_t* out) {
+    const Off* off = static_cast<const Off*>(P.offsets);
+    const int64_t beg = off[src], end = off[src + 1];
+    const int64_t deg = (beg >= 0 && beg <= end && end <= P.nnz) ? end - beg : 0;
+    for (int b = 0; 4 * b <= P.k; ++b) {
+        const uint4 r = philox10(make_uint4(static_cast<uint32_t>(src), P.epoch, P.w2, stream_word3(0, 0, b)),
+                                 P.key0, P.key1);
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+        for (int j = 0; j < 4; ++j) {
+            const int t = 4 * b + j;
+            if (t > P.k) break;
+            int32_t v;
+            if (t == 0) {
+                v = -1;
+                if (deg > 0) {
+                    const int32_t pos = P.indices[beg + scale_u32(w[0], deg)];
+                    v = (pos >= 0 && pos < P.n) ? pos : -1;
+                }
+            } else {
+                v = static_cast<int32_t>(scale_u32(w[j], P.n));
+            }
+            out[t] = v;
+        }
+    }
 }
 
 // Adds the running losses of the wave's groups (`l` on every lane of a
@@ -447,6 +565,61 @@ __device__ __forceinline__ void wave_add_loss(double* dst, float l, int gl) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0 && v != 0.0f)
         __hip_atomic_fetch_add(dst, static_cast<double>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kLdsBlock = 1024;   // one workgroup of 16 waves trains a level held in LDS
+
+// LDS bytes a level trained in one workgroup needs: its rows plus the
+// sample table of one epoch.
+__host__ __device__ constexpr int64_t lds_level_bytes(int64_t n, int d, int elem_bytes, int k) {
+    return n * d * elem_bytes + n * (1 + k) * 4;
+}
+
+// Trains all P.e_total epochs of one level (or batched job) inside the
+// calling workgroup of kLdsBlock threads, its rows held in `lds` (the LDS
+// hot copy: read from HBM once, written back once).  Every epoch first draws
+// the samples of all sources into an LDS table (all threads at once, the
+// same Philox draws as the per-epoch kernel), then the waves visit the
+// sources with the update chain on the LDS rows, a workgroup barrier after
+// each phase: Algorithm 3's epochs in order, the sources of an epoch
+// concurrent over the workgroup's 16 waves.  lr' = P.lr0 max(1 - j/e, 1e-4).
+template <bool BF16, int D, int KMAX, class Off>
+__device__ __forceinline__ void train_rows_in_lds(TrainParams P, unsigned char* lds) {
+    using Elem = typename RowIO<BF16>::Elem;
+    constexpr int L = Lanes<BF16, D>::kL;
+    constexpr int G = Lanes<BF16, D>::kG;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / L, gl = lane % L;
+    const int wave = threadIdx.x >> 6;
+    Elem* rows = reinterpret_cast<Elem*>(lds);
+    int32_t* table = reinterpret_cast<int32_t*>(lds + P.n * D * sizeof(Elem));
+    const int64_t words = P.n * D * static_cast<int64_t>(sizeof(Elem)) / 4;
+    uint32_t* glob = static_cast<uint32_t*>(P.emb);
+    for (int64_t i = threadIdx.x; i < words; i += kLdsBlock) reinterpret_cast<uint32_t*>(rows)[i] = glob[i];
+    __syncthreads();
+    TrainParams Q = P;
+    Q.emb = rows;
+    Q.samples = table;
+    for (int j = 0; j < P.e_total; ++j) {
+        Q.epoch = static_cast<uint32_t>(j);
+        const double f = 1.0 - static_cast<double>(j) / static_cast<double>(P.e_total);
+        Q.lr = static_cast<float>(static_cast<double>(P.lr0) * (f > 1e-4 ? f : 1e-4));
+        Q.loss = P.loss ? P.loss + j : nullptr;
+        for (int64_t v = threadIdx.x; v < P.n; v += kLdsBlock) {
+            draw_source<Off>(Q, v, table + v * (1 + P.k));
+            if (Q.record) {
+                for (int t = 0; t <= P.k; ++t) Q.record[v * (1 + P.k) + t] = table[v * (1 + P.k) + t];
+            }
+        }
+        __syncthreads();
+        for (int64_t base = static_cast<int64_t>(wave) * G; base < P.n; base += (kLdsBlock / 64) * G) {
+            const int64_t slot = base + grp;
+            const float l = visit<BF16, D, KMAX, Off, kLds, LdsRowIO<BF16>>(Q, slot, slot < P.n, gl);
+            if (Q.loss) wave_add_loss<L>(Q.loss, l, gl);
+        }
+        __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < words; i += kLdsBlock) glob[i] = reinterpret_cast<uint32_t*>(rows)[i];
 }
 
 }  // namespace train_detail

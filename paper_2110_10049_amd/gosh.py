@@ -86,6 +86,7 @@ _SIGNATURES = [
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
     ("gosh_set_loss_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_set_resident_epochs", C.c_int, [_P, C.c_int64]),
+    ("gosh_set_lds_levels", C.c_int, [_P, C.c_int64]),
     ("gosh_set_draw_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_trim", C.c_int, [_P]),
     ("gosh_set_coarsen_mode", C.c_int, [_P, C.c_int, C.c_int64]),
@@ -226,6 +227,10 @@ class Context:
     def set_resident_epochs(self, max_vertices: int):
         """All epochs of a level of at most max_vertices vertices in one launch (0 = off)."""
         self.check(self._L.gosh_set_resident_epochs(self.h, max_vertices))
+
+    def set_lds_levels(self, max_vertices: int):
+        """Levels of at most max_vertices vertices whose rows fit in LDS train in one workgroup (0 = off)."""
+        self.check(self._L.gosh_set_lds_levels(self.h, max_vertices))
 
     def set_loss_record(self, loss: "torch.Tensor | None"):
         """Running loss per epoch of later gosh_train calls, added to a float64
