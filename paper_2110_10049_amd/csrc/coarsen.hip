@@ -355,6 +355,292 @@ __global__ void k_offsets_lb(const K* ukeys, int64_t m, int64_t n_next, int bb, 
     }
 }
 
+// ---------------------------------------------------------------- coarse graph by cluster segments
+// The coarse row of cluster c is the sorted set of clusters adjacent to its
+// members.  Members are grouped by cluster (a sort of the n vertices by map),
+// so the entries of one cluster form one contiguous segment of the level's
+// entries in member order; each entry is replaced by its neighbour's cluster
+// (or kSegSent inside c).  A segment's distinct clusters are collected in a
+// bitmap over the next level's vertex ids and read back in bit order, which
+// is ascending: one wave with an LDS bitmap per segment of at most kSegSmall
+// entries; longer segments (hub clusters) are cut into chunks of kGiantChunk
+// entries, one workgroup each, whose LDS bitmaps are OR-ed into one global
+// bitmap per cluster.
+constexpr int kSegSmall = 4096;     // entries of a segment deduplicated by one wave
+constexpr int kGiantChunk = 16384;  // entries of a long segment per workgroup
+constexpr int kSegWaves = 4;
+constexpr int64_t kSegMaxWords = 8192;   // bitmap words per wave (next level of at most 262,144 vertices)
+constexpr uint32_t kSegSent = 0xFFFFFFFFu;
+
+template <class Off>
+__global__ void k_member_deg(const Off* off, const uint32_t* mem, int64_t n, int32_t* mdeg) {
+    GRID_STRIDE(i, n) {
+        const int64_t v = mem[i];
+        mdeg[i] = static_cast<int32_t>(static_cast<int64_t>(off[v + 1]) - static_cast<int64_t>(off[v]));
+    }
+}
+
+// cstart[c] = first member position of cluster c (lower bound in the sorted
+// cluster keys), segstart[c] = its first entry; both for c in [0, n_next]
+__global__ void k_seg_starts(const uint32_t* ckey, int64_t n, int64_t n_next, const int64_t* E, int64_t nnz,
+                             int64_t* segstart) {
+    GRID_STRIDE(c, n_next + 1) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (static_cast<int64_t>(ckey[mid]) < c) lo = mid + 1;
+            else hi = mid;
+        }
+        segstart[c] = lo < n ? E[lo] : nnz;
+    }
+}
+
+// dbase[v] = E[position of v among the members] - off[v], so that entry p of
+// row v goes to raw[dbase[v] + p]
+template <class Off>
+__global__ void k_dest_base(const Off* off, const uint32_t* mem, const int64_t* E, int64_t n, int64_t* dbase) {
+    GRID_STRIDE(i, n) {
+        const int64_t v = mem[i];
+        dbase[v] = E[i] - static_cast<int64_t>(off[v]);
+    }
+}
+
+// raw[dbase[v] + p] = cluster of entry p's neighbour (kSegSent inside v's cluster)
+__global__ void k_gather_raw(const int32_t* src, const int32_t* idx, int64_t nnz, const int64_t* dbase,
+                             const int32_t* map, uint32_t* raw) {
+    GRID_STRIDE(p, nnz) {
+        const int32_t v = src[p];
+        const uint32_t m = static_cast<uint32_t>(map[idx[p]]);
+        raw[dbase[v] + p] = m != static_cast<uint32_t>(map[v]) ? m : kSegSent;
+    }
+}
+
+// orders the wave's LDS writes before its later LDS reads
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per small segment: its clusters OR-ed into the wave's bitmap over
+// the next level's vertex ids (W 32-bit words of dynamic LDS, only the words
+// between the segment's smallest and largest id cleared and scanned), then
+// the distinct ids written back in place, ascending (bit order), each lane
+// placing its word's ids after a wave prefix sum of the popcounts;
+// cnt[c] = their number.
+__global__ __launch_bounds__(64 * kSegWaves) void k_dedup_small(const int64_t* segstart, int64_t n_next, int W,
+                                                                uint32_t* raw, int32_t* cnt) {
+    extern __shared__ uint32_t seg_bitmaps[];
+    const int lane = threadIdx.x & 63;
+    uint32_t* bm = seg_bitmaps + static_cast<int64_t>(threadIdx.x >> 6) * W;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * kSegWaves;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * kSegWaves + (threadIdx.x >> 6); c < n_next; c += nw) {
+        const int64_t s0 = segstart[c];
+        const int64_t len = segstart[c + 1] - s0;
+        if (len > kSegSmall) continue;   // a big segment: sorted with the others
+        uint32_t kmin = kSegSent, kmax = 0;
+        for (int64_t i = lane; i < len; i += 64) {
+            const uint32_t x = raw[s0 + i];
+            if (x != kSegSent) {
+                kmin = min(kmin, x);
+                kmax = max(kmax, x);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmin), o, 64)));
+            kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), o, 64)));
+        }
+        if (kmin > kmax) {   // no entry leaves the cluster
+            if (lane == 0) cnt[c] = 0;
+            continue;
+        }
+        const int w0 = static_cast<int>(kmin >> 5), w1 = static_cast<int>(kmax >> 5);
+        for (int w = w0 + lane; w <= w1; w += 64) bm[w] = 0u;
+        wave_lds_sync();
+        for (int64_t i = lane; i < len; i += 64) {
+            const uint32_t x = raw[s0 + i];
+            if (x != kSegSent) atomicOr(&bm[x >> 5], 1u << (x & 31u));
+        }
+        wave_lds_sync();
+        int64_t total = 0;
+        for (int base = w0; base <= w1; base += 64) {
+            const int w = base + lane;
+            uint32_t word = w <= w1 ? bm[w] : 0u;
+            const int pc = __popc(word);
+            int incl = pc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            int64_t pos = s0 + total + (incl - pc);
+            while (word) {
+                const int bit = __ffs(word) - 1;
+                raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
+                word &= word - 1u;
+            }
+            total += __shfl(incl, 63, 64);
+        }
+        if (lane == 0) cnt[c] = static_cast<int32_t>(total);
+        wave_lds_sync();
+    }
+}
+
+// Segments longer than kSegSmall ("giant": hub clusters) are cut into chunks
+// of kGiantChunk entries: cc[c] = chunks of cluster c (0 if not giant),
+// gf[c] = 1 for a giant.
+__global__ void k_giant_flags(const int64_t* segstart, int64_t n_next, int32_t* gf, int32_t* cc) {
+    GRID_STRIDE(c, n_next) {
+        const int64_t len = segstart[c + 1] - segstart[c];
+        const bool g = len > kSegSmall;
+        gf[c] = g ? 1 : 0;
+        cc[c] = g ? static_cast<int32_t>(ceil_div(len, kGiantChunk)) : 0;
+    }
+}
+
+constexpr int kGiantThreads = 1024;
+
+// One workgroup per chunk of a giant segment: the chunk's clusters OR-ed
+// into the workgroup's LDS bitmap, then its non-zero words OR-ed into the
+// giant's global bitmap gbm[gidx[c] * W ..].  Chunk t belongs to the last
+// cluster c with cpos[c] <= t (cpos: exclusive prefix of cc; clusters without
+// chunks share their start with the next cluster, so the last one is a giant).
+__global__ __launch_bounds__(kGiantThreads) void k_giant_chunks(const int64_t* segstart, int64_t n_next,
+                                                                const int64_t* cpos, int64_t chunks,
+                                                                const int64_t* gidx, int W, const uint32_t* raw,
+                                                                uint32_t* gbm) {
+    extern __shared__ uint32_t seg_bitmaps[];
+    __shared__ uint32_t red[2][kGiantThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t t = blockIdx.x; t < chunks; t += gridDim.x) {
+        int64_t lo = 0, hi = n_next;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (cpos[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const int64_t cl = lo;
+        const int64_t s0 = segstart[cl] + (t - cpos[cl]) * kGiantChunk;
+        const int64_t len = min(static_cast<int64_t>(kGiantChunk), segstart[cl + 1] - s0);
+        uint32_t kmin = kSegSent, kmax = 0;
+        for (int64_t i = threadIdx.x; i < len; i += kGiantThreads) {
+            const uint32_t x = raw[s0 + i];
+            if (x != kSegSent) {
+                kmin = min(kmin, x);
+                kmax = max(kmax, x);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmin), o, 64)));
+            kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), o, 64)));
+        }
+        if (lane == 0) {
+            red[0][wv] = kmin;
+            red[1][wv] = kmax;
+        }
+        __syncthreads();
+        kmin = kSegSent;
+        kmax = 0;
+        for (int i = 0; i < kGiantThreads / 64; ++i) {
+            kmin = min(kmin, red[0][i]);
+            kmax = max(kmax, red[1][i]);
+        }
+        if (kmin <= kmax) {   // block-uniform
+            const int w0 = static_cast<int>(kmin >> 5), w1 = static_cast<int>(kmax >> 5);
+            for (int w = w0 + static_cast<int>(threadIdx.x); w <= w1; w += kGiantThreads) seg_bitmaps[w] = 0u;
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < len; i += kGiantThreads) {
+                const uint32_t x = raw[s0 + i];
+                if (x != kSegSent) atomicOr(&seg_bitmaps[x >> 5], 1u << (x & 31u));
+            }
+            __syncthreads();
+            uint32_t* g = gbm + gidx[cl] * static_cast<int64_t>(W);
+            for (int w = w0 + static_cast<int>(threadIdx.x); w <= w1; w += kGiantThreads) {
+                const uint32_t word = seg_bitmaps[w];
+                if (word) atomicOr(&g[w], word);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Block-wide exclusive prefix of v (blocks of kGiantThreads); *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[kGiantThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int i = 0; i < kGiantThreads / 64; ++i) {
+        if (i < w) before += wsum[i];
+        all += wsum[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// One block per giant (cluster gc[g]): count of its global bitmap (out ==
+// nullptr) or its ids written ascending from indices[offs[c]].
+__global__ __launch_bounds__(kGiantThreads) void k_giant_emit(const int32_t* gc, int64_t G, int W, const uint32_t* gbm,
+                                                              int32_t* cnt, const int64_t* offs, int32_t* indices) {
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        const int64_t cl = gc[g];
+        const uint32_t* bm = gbm + g * static_cast<int64_t>(W);
+        int64_t total = 0;
+        for (int base = 0; base < W; base += kGiantThreads) {
+            const int w = base + static_cast<int>(threadIdx.x);
+            uint32_t word = w < W ? bm[w] : 0u;
+            int all = 0;
+            const int before = block_excl_scan(__popc(word), &all);
+            if (indices) {
+                int64_t pos = offs[cl] + total + before;
+                while (word) {
+                    const int bit = __ffs(word) - 1;
+                    indices[pos++] = (w << 5) | bit;
+                    word &= word - 1u;
+                }
+            }
+            total += all;
+        }
+        if (!indices && threadIdx.x == 0) cnt[cl] = static_cast<int32_t>(total);
+    }
+}
+
+// gc[gidx[c]] = c for every giant
+__global__ void k_giant_list(const int32_t* gf, const int64_t* gidx, int64_t n_next, int32_t* gc) {
+    GRID_STRIDE(c, n_next) {
+        if (gf[c]) gc[gidx[c]] = static_cast<int32_t>(c);
+    }
+}
+
+__global__ void k_iota_u32(uint32_t* a, int64_t n) {
+    GRID_STRIDE(i, n) a[i] = static_cast<uint32_t>(i);
+}
+
+template <class Off>
+__global__ void k_seg_offsets(const int64_t* offs, int64_t n_next, int64_t nnz_next, Off* offsets) {
+    GRID_STRIDE(c, n_next + 1) offsets[c] = static_cast<Off>(c < n_next ? offs[c] : nnz_next);
+}
+
+// small segments: their distinct clusters (already in place, ascending) copied out; one wave per cluster
+__global__ void k_small_out(const int64_t* segstart, int64_t n_next, const int32_t* cnt, const int64_t* offs,
+                            const uint32_t* raw, int32_t* indices) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); c < n_next;
+         c += static_cast<int64_t>(gridDim.x) * wpb) {
+        const int64_t s0 = segstart[c];
+        if (segstart[c + 1] - s0 > kSegSmall) continue;
+        const int64_t o = offs[c], k = cnt[c];
+        for (int64_t i = lane; i < k; i += 64) indices[o + i] = static_cast<int32_t>(raw[s0 + i]);
+    }
+}
+
 // ---------------------------------------------------------------- validation
 // Offsets must start at 0, end at nnz and never decrease before any kernel
 // may read a row.
@@ -476,6 +762,115 @@ int64_t build_coarse(Ctx* c, const int32_t* src, const int32_t* idx, int64_t nnz
     return nnz_next;
 }
 
+// Coarse CSR by cluster segments (see k_dedup_small, k_giant_chunks).  src:
+// row of every entry.  Returns nnz' and sets *off_out / *idx_out, or returns
+// -1 (nothing allocated) when the next level is too large for the LDS
+// bitmaps; the caller then builds the level with build_coarse.
+template <class Off>
+int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32_t* idx, int64_t n, int64_t nnz,
+                         const int32_t* map, int64_t n_next, bool off64, void** off_out, int32_t** idx_out) {
+    const int bb = std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(n_next - 1, 0))));   // sort bits of a cluster id
+    const int64_t W = ceil_div(std::max<int64_t>(n_next, 1), 32);   // bitmap words per wave and per giant
+    if (W > kSegMaxWords) return -1;
+    // members grouped by cluster, in id order within a cluster
+    DevBuf<uint32_t> ckey(c, n), ckey_tmp(c, n), mem(c, n), mem_tmp(c, n);
+    GOSH_HIP(hipMemcpyAsync(ckey.p, map, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_iota_u32, grid_for(n), dim3(kThreads), 0, c->stream, mem.p, n);
+    GOSH_HIP(hipGetLastError());
+    radix_sort_u32(c, ckey.p, ckey_tmp.p, mem.p, mem_tmp.p, n, bb);
+    ckey_tmp.reset();
+    mem_tmp.reset();
+    DevBuf<int64_t> E(c, n);
+    {
+        DevBuf<int32_t> mdeg(c, n);
+        hipLaunchKernelGGL((k_member_deg<Off>), grid_for(n), dim3(kThreads), 0, c->stream, off, mem.p, n, mdeg.p);
+        GOSH_HIP(hipGetLastError());
+        scan_i32_to_i64(c, mdeg.p, E.p, n, nullptr);
+    }
+    DevBuf<int64_t> segstart(c, n_next + 1);
+    hipLaunchKernelGGL(k_seg_starts, grid_for(n_next + 1), dim3(kThreads), 0, c->stream, ckey.p, n, n_next, E.p, nnz,
+                       segstart.p);
+    GOSH_HIP(hipGetLastError());
+    DevBuf<uint32_t> raw(c, std::max<int64_t>(nnz, 1));
+    {
+        DevBuf<int64_t> dbase(c, n);
+        hipLaunchKernelGGL((k_dest_base<Off>), grid_for(n), dim3(kThreads), 0, c->stream, off, mem.p, E.p, n,
+                           dbase.p);
+        GOSH_HIP(hipGetLastError());
+        if (nnz > 0) {
+            hipLaunchKernelGGL(k_gather_raw, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz, dbase.p,
+                               map, raw.p);
+            GOSH_HIP(hipGetLastError());
+        }
+    }
+    E.reset();
+    mem.reset();
+    ckey.reset();
+
+    // giant segments: chunk count and list
+    DevBuf<int32_t> gf(c, n_next), cc(c, n_next);
+    DevBuf<int64_t> gidx(c, n_next), cpos(c, n_next);
+    hipLaunchKernelGGL(k_giant_flags, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, n_next, gf.p, cc.p);
+    GOSH_HIP(hipGetLastError());
+    int64_t G = 0, chunks = 0;
+    scan_i32_to_i64(c, gf.p, gidx.p, n_next, &G);
+    scan_i32_to_i64(c, cc.p, cpos.p, n_next, &chunks);
+    cc.reset();
+
+    DevBuf<int32_t> cnt(c, n_next);
+    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(W) * kSegWaves;
+    GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dedup_small),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    hipLaunchKernelGGL(k_dedup_small, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(n_next, kSegWaves), 8192))),
+                       dim3(64 * kSegWaves), lds, c->stream, segstart.p, n_next, static_cast<int>(W), raw.p, cnt.p);
+    GOSH_HIP(hipGetLastError());
+    DevBuf<int32_t> gc(c, std::max<int64_t>(G, 1));
+    DevBuf<uint32_t> gbm(c, std::max<int64_t>(G * W, 1));
+    if (G > 0) {
+        GOSH_HIP(hipMemsetAsync(gbm.p, 0, sizeof(uint32_t) * G * W, c->stream));
+        hipLaunchKernelGGL(k_giant_list, grid_for(n_next), dim3(kThreads), 0, c->stream, gf.p, gidx.p, n_next, gc.p);
+        GOSH_HIP(hipGetLastError());
+        const size_t glds = sizeof(uint32_t) * static_cast<size_t>(W);
+        GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_giant_chunks),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(glds)));
+        hipLaunchKernelGGL(k_giant_chunks, dim3(static_cast<unsigned>(std::min<int64_t>(chunks, 65536))),
+                           dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, cpos.p, chunks, gidx.p,
+                           static_cast<int>(W), raw.p, gbm.p);
+        GOSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_giant_emit, dim3(static_cast<unsigned>(std::min<int64_t>(G, 4096))), dim3(kGiantThreads), 0,
+                           c->stream, gc.p, G, static_cast<int>(W), gbm.p, cnt.p, nullptr, nullptr);
+        GOSH_HIP(hipGetLastError());
+    }
+    gidx.reset();
+    cpos.reset();
+    gf.reset();
+
+    // offsets from the distinct counts, then the rows
+    DevBuf<int64_t> offs(c, n_next);
+    int64_t nnz_next = 0;
+    scan_i32_to_i64(c, cnt.p, offs.p, n_next, &nnz_next);
+    int32_t* indices = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * std::max<int64_t>(nnz_next, 1)));
+    void* offsets = c->alloc((off64 ? 8 : 4) * (n_next + 1));
+    if (off64)
+        hipLaunchKernelGGL((k_seg_offsets<int64_t>), grid_for(n_next + 1), dim3(kThreads), 0, c->stream, offs.p,
+                           n_next, nnz_next, static_cast<int64_t*>(offsets));
+    else
+        hipLaunchKernelGGL((k_seg_offsets<int32_t>), grid_for(n_next + 1), dim3(kThreads), 0, c->stream, offs.p,
+                           n_next, nnz_next, static_cast<int32_t*>(offsets));
+    GOSH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_small_out, grid_for(n_next, kThreads / 64), dim3(kThreads), 0, c->stream, segstart.p,
+                       n_next, cnt.p, offs.p, raw.p, indices);
+    GOSH_HIP(hipGetLastError());
+    if (G > 0) {
+        hipLaunchKernelGGL(k_giant_emit, dim3(static_cast<unsigned>(std::min<int64_t>(G, 4096))), dim3(kGiantThreads), 0,
+                           c->stream, gc.p, G, static_cast<int>(W), gbm.p, cnt.p, offs.p, indices);
+        GOSH_HIP(hipGetLastError());
+    }
+    *off_out = offsets;
+    *idx_out = indices;
+    return nnz_next;
+}
+
 // Row of every entry (one wave per vertex streams its row).
 template <class Off>
 DevBuf<int32_t> expand_rows(Ctx* c, const Off* off, int64_t n, int64_t nnz) {
@@ -554,16 +949,21 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     // scan each segment with a whole wave
     DevBuf<uint8_t> state(c, n);
     fill(c, state.p, n, 0);
-    for (int64_t round = 0;; ++round) {
-        GOSH_REQUIRE(round <= n + 1, GOSH_E_DEVICE, "coarsening rounds did not converge");
-        GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
-        if (dense)
-            hipLaunchKernelGGL(k_round_wave, grid_reduce(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
-                               lstart.p, lower.p, state.p, scratch_u64(c, 1));
-        else
-            hipLaunchKernelGGL(k_round, grid_reduce(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                               scratch_u64(c, 1));
-        GOSH_HIP(hipGetLastError());
+    // two rounds per host check (a round over decided vertices changes
+    // nothing, and the R-MAT levels take 2-4): the count read back is the
+    // second round's
+    for (int64_t round = 0;; round += 2) {
+        GOSH_REQUIRE(round <= n + 2, GOSH_E_DEVICE, "coarsening rounds did not converge");
+        for (int r = 0; r < 2; ++r) {
+            GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
+            if (dense)
+                hipLaunchKernelGGL(k_round_wave, grid_reduce(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
+                                   lstart.p, lower.p, state.p, scratch_u64(c, 1));
+            else
+                hipLaunchKernelGGL(k_round, grid_reduce(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p,
+                                   state.p, scratch_u64(c, 1));
+            GOSH_HIP(hipGetLastError());
+        }
         if (read_u64(c, scratch_u64(c, 1)) == 0) break;
     }
 
@@ -667,14 +1067,19 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     rank.reset();
     perm.reset();
 
-    // coarse graph: distinct pairs (map v, map u), map v != map u, rows ascending
+    // coarse graph: distinct pairs (map v, map u), map v != map u, rows
+    // ascending; by cluster segments, or by one sort of all pair keys
     void* noff = nullptr;
     int32_t* nidx = nullptr;
-    int64_t nnz_next;
-    if (2 * std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(n_next - 1, 0)))) <= 32)
-        nnz_next = build_coarse<uint32_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
-    else
-        nnz_next = build_coarse<uint64_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+    int64_t nnz_next = -1;
+    if (c->coarse_build == 0 && n > 0 && nnz < (int64_t(1) << 31))
+        nnz_next = build_coarse_seg<Off>(c, off, src, idx, n, nnz, L.map, n_next, L.off64, &noff, &nidx);
+    if (nnz_next < 0) {
+        if (2 * std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(n_next - 1, 0)))) <= 32)
+            nnz_next = build_coarse<uint32_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+        else
+            nnz_next = build_coarse<uint64_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
+    }
     // the assignment flag was written before the syncs inside build_coarse
     GOSH_REQUIRE(read_flags(c, bad) == 0, GOSH_E_BAD_GRAPH,
                  "coarsening left a vertex without a cluster (graph not symmetric?)");

@@ -52,6 +52,7 @@ struct Ctx {
     double* loss = nullptr;    // running loss per epoch of gosh_train (device, caller-owned)
     int64_t loss_cap = 0;
     int coarsen_mode = GOSH_COARSEN_EXACT;
+    int coarse_build = 0;      // coarse graph: 0 by cluster segments (one sort of all pair keys where they do not fit), 1 always the sort
     int64_t claim_batch = 0;   // lock-and-skip ranks per launch (0: max(64, n/64))
     std::string err;
     // Size-bucketed cache of freed device blocks, reused before hipMalloc.
