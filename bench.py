@@ -9,10 +9,11 @@ split), d = 128, k = 3 negatives, 600 epochs over all levels (p = 0.3),
 lr = 0.045, coarsening threshold 100.  The headline run stores rows in BF16
 (stochastic rounding, FP32 arithmetic); the same workload with FP32 rows is
 timed beside it, and both final embeddings are scored by link-prediction
-AUC on the held-out 20%.  Rows of negative samples are written with plain
-stores (the paper's lock-free writes) on levels of at least 262,144 vertices
-(level 0 of the scale-20 graph) and with atomic adds elsewhere; positive and
-source rows always use atomic adds (--plain-neg-min 0: atomic adds
+AUC on the held-out 20%.  On levels of at least 262,144 vertices (level 0
+of the scale-20 graph) rows of negative samples, and every row of at most
+average degree, are written with plain stores (the paper's lock-free
+writes), hub rows with atomic commits; smaller levels commit every row
+atomically (--plain-neg-min 0 --plain-light-min 0: atomic commits
 everywhere).
 
 value = executed UpdateEmbed calls (edge-samples) per second of step wall
@@ -112,6 +113,9 @@ def parse():
     ap.add_argument("--plain-neg-min", type=int, default=262144,
                     help="plain stores for negative rows on levels of at least this many vertices (0: atomic adds "
                          "everywhere)")
+    ap.add_argument("--plain-light-min", type=int, default=262144,
+                    help="plain stores for rows of at most average degree on levels of at least this many vertices "
+                         "(0: off)")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-loss", action="store_true", help="skip the untimed running-loss passes")
     ap.add_argument("--lds-levels", type=int, default=0,
@@ -734,6 +738,7 @@ def main_workload(a):
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     ctx.set_plain_negatives(a.plain_neg_min)
+    ctx.set_plain_light_rows(a.plain_light_min)
     ctx.set_coarsen_mode(G.GOSH_COARSEN_LOCK_SKIP if a.coarsen == "lock-skip" else G.GOSH_COARSEN_EXACT)
     ctx.set_lds_levels(a.lds_levels)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
@@ -848,7 +853,8 @@ def main_workload(a):
                                f"lr={lr}, threshold={threshold}, BF16 rows + SR",
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds, "epoch_unit": "passes",
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
-                   "plain_negative_stores_min_vertices": a.plain_neg_min, "coarsening": a.coarsen,
+                   "plain_negative_stores_min_vertices": a.plain_neg_min,
+                   "plain_light_rows_min_vertices": a.plain_light_min, "coarsening": a.coarsen,
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),

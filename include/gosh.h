@@ -182,6 +182,19 @@ gosh_status gosh_set_lds_levels(gosh_ctx* ctx, int64_t max_vertices);
  * deterministic mode.  min_vertices >= 0. */
 gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices);
 
+/* Write discipline by degree (Section 3.1's lock-free sources; Section 4.1's
+ * hub definition).  With min_vertices > 0, gosh_train writes every row of
+ * degree at most the level's average (deg * n <= nnz: not a hub) with plain
+ * stores of the new value -- the source, the positive and the negatives
+ * alike -- on levels of at least min_vertices vertices, and keeps the atomic
+ * commits for hub rows.  A light row is touched a few times per epoch, so a
+ * store rarely overwrites a concurrent update, while hub rows, which take
+ * most positive updates, lose none.  The atomic units bound the training
+ * kernel, and most rows are light.  Also applied in deterministic mode,
+ * where it changes no bit (one visit at a time).  Levels it applies to keep
+ * one launch per epoch.  0 (the default) turns it off.  min_vertices >= 0. */
+gosh_status gosh_set_plain_light_rows(gosh_ctx* ctx, int64_t min_vertices);
+
 /* Running loss of training (the objective of Section 2, the logistic loss of
  * the classifier sigma(M[v].M[u]) on the positive and negative samples).
  * When loss_dev is not NULL, every later gosh_train call adds to

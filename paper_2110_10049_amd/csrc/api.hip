@@ -264,6 +264,12 @@ gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices) {
     return GOSH_OK;
 }
 
+gosh_status gosh_set_plain_light_rows(gosh_ctx* ctx, int64_t min_vertices) {
+    if (!ctx || min_vertices < 0) return GOSH_E_INVALID_ARG;
+    ctx->c.plain_light_min = min_vertices;
+    return GOSH_OK;
+}
+
 gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices) {
     if (!ctx || max_vertices < 0) return GOSH_E_INVALID_ARG;
     ctx->c.resident_max = max_vertices;

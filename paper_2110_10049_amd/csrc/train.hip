@@ -342,6 +342,9 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     P.e_total = epochs;
     P.lr0 = lr;
     P.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && L.n >= c->plain_neg_min) ? 1 : 0;
+    // light rows stored plainly; also in deterministic mode, where one visit
+    // at a time makes a plain store equal to the atomic commit
+    P.light_below = (c->plain_light_min > 0 && L.n >= c->plain_light_min) ? L.nnz / L.n + 1 : 0;
     if (c->record) {
         GOSH_REQUIRE(c->record_cap >= L.n * (1 + k), GOSH_E_INVALID_ARG,
                      "draw record buffer holds fewer than n * (1 + k) entries");
@@ -350,7 +353,8 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     GOSH_REQUIRE(!c->loss || c->loss_cap >= epochs, GOSH_E_INVALID_ARG,
                  "loss record buffer holds fewer entries than the call's epochs");
     const int64_t lds_bytes = lds_level_bytes(L.n, d, dt == GOSH_BF16 ? 2 : 4, k);
-    if (!c->deterministic && span == 1 && P.plain_neg == 0 && L.n <= c->lds_max && lds_bytes <= kLdsMaxBytes) {
+    const bool plain = P.plain_neg != 0 || P.light_below != 0;
+    if (!c->deterministic && span == 1 && !plain && L.n <= c->lds_max && lds_bytes <= kLdsMaxBytes) {
         // the level's rows and one epoch's samples in one workgroup's LDS
         const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64, true)
                                                  : resident_d<false>(d, k, L.off64, true);
@@ -361,7 +365,7 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
         P.loss = c->loss;
         void* args[] = {&P};
         GOSH_HIP(hipLaunchKernel(R.fn, dim3(1), dim3(kLdsBlock), args, static_cast<size_t>(lds_bytes), c->stream));
-    } else if (!c->deterministic && span == 1 && epochs > 1 && L.n <= c->resident_max && P.plain_neg == 0) {
+    } else if (!c->deterministic && span == 1 && epochs > 1 && L.n <= c->resident_max && !plain) {
         // all epochs in one cooperative launch with device-wide barriers
         const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64) : resident_d<false>(d, k, L.off64);
         GOSH_REQUIRE(R.fn, GOSH_E_INVALID_ARG, "unsupported training shape");

@@ -38,6 +38,11 @@ struct TrainParams {
     int32_t e_total;
     float lr0;
     int32_t plain_neg;        // negatives written with plain stores instead of atomic adds
+    // rows of degree below light_below written with plain stores (sources,
+    // positives and negatives alike), 0 for none; the host sets it to
+    // floor(nnz / n) + 1, so light rows are the complement of Section 4.1's
+    // hubs (deg * n <= nnz), and hub rows keep their atomic commits
+    int64_t light_below;
     int32_t* record;          // optional: samples drawn by each visit, [n][1+k]
     double* loss;             // optional: running loss per epoch of the launch (index = epoch - first)
 };
@@ -301,7 +306,9 @@ __device__ __forceinline__ float softplusf_(float z) {
 // which the callers precount.  BF16 rounding bits come from the stream (sid,
 // epoch, w2, kind sr_kind | slot t or 255 | block blk_hi << 8 | gl mod d/8).
 // COH: loads bypass the non-coherent caches (rows written by other waves of
-// the same launch).  Returns, when want_loss, the visit's running loss: the
+// the same launch).  plain: rows written with plain stores of the new values
+// instead of atomic commits of the change (bit t sample slot t, bit 31 the
+// source).  Returns, when want_loss, the visit's running loss: the
 // Section 2 objective of each executed update at the dot it reads (the same
 // value on every lane of the group); 0 otherwise.
 template <bool BF16, int D, int KMAX, bool COH, class IO = RowIO<BF16>>
@@ -310,7 +317,7 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
                                               const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
                                               uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
                                               uint32_t key0, uint32_t key1, unsigned long long* updates, int gl,
-                                              bool plain_neg = false, bool want_loss = false) {
+                                              uint32_t plain = 0u, bool want_loss = false) {
     using Ly = Lanes<BF16, D>;
     constexpr int L = Ly::kL;
     constexpr int E = Ly::kEPL;
@@ -378,7 +385,7 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
                 v[2 * i + 1] = fmaf(g, s[2 * i + 1], bf16_hi(mw[t][i]));
             }
             uint32_t out[W];
-            if (t > 0 && plain_neg) IO::template commit<D, true>(Mo, ut, gl, mw[t], v, bits, out);
+            if ((plain >> t) & 1u) IO::template commit<D, true>(Mo, ut, gl, mw[t], v, bits, out);
             else IO::template commit<D>(Mo, ut, gl, mw[t], v, bits, out);
 #pragma unroll
             for (int i = 0; i < W; ++i) mw[t][i] = out[i];
@@ -387,7 +394,8 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
         if (done) {
             const uint4 bits = philox10(make_uint4(sid, epoch, w2, stream_word3(sr_kind, 0xFFu, blk)), key0, key1);
             uint32_t out[W];
-            IO::template commit<D>(Ms, src, gl, sw, s, bits, out);
+            if (plain >> 31) IO::template commit<D, true>(Ms, src, gl, sw, s, bits, out);
+            else IO::template commit<D>(Ms, src, gl, sw, s, bits, out);
         }
     } else {
         float s[E];
@@ -433,10 +441,13 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
             float dx[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
+                // not contracted: the row in registers is the rounded change
+                // added to the row, the value an uncontended atomic add leaves
+#pragma clang fp contract(off)
                 dx[e] = g * s[e];
                 m[t][e] += dx[e];
             }
-            if (t > 0 && plain_neg) IO::template store<D>(Mo, ut, gl, m[t]);
+            if ((plain >> t) & 1u) IO::template store<D>(Mo, ut, gl, m[t]);
             else IO::template add<D>(Mo, ut, gl, dx);
             ++done;
         }
@@ -444,7 +455,14 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
             float dx[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) dx[e] = s[e] - s0[e];
-            IO::template add<D>(Ms, src, gl, dx);
+            if (plain >> 31) {
+                // the value an uncontended atomic add of dx leaves
+#pragma unroll
+                for (int e = 0; e < E; ++e) s[e] = s0[e] + dx[e];
+                IO::template store<D>(Ms, src, gl, s);
+            } else {
+                IO::template add<D>(Ms, src, gl, dx);
+            }
         }
     }
     return lsum;
@@ -461,6 +479,7 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
     const int k = P.k;
 
     int64_t src = slot;
+    uint32_t plain = 0u;   // rows stored plainly: bit t sample slot t, bit 31 the source
     int32_t u[KMAX + 1];
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) u[t] = -1;
@@ -517,12 +536,28 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
                 for (int t = 0; t <= KMAX; ++t)
                     if (t <= k) P.record[src * (1 + k) + t] = u[t];
             }
+            if constexpr (MODE == kEpoch || MODE == kSequential) {
+                if (P.light_below > 0) {
+                    // light rows are stored plainly; the degree loads run
+                    // beside the row loads of the chain
+                    if (deg < P.light_below) plain |= 1u << 31;
+#pragma unroll
+                    for (int t = 0; t <= KMAX; ++t) {
+                        if (t <= k && u[t] >= 0) {
+                            const int64_t dt = static_cast<int64_t>(off[u[t] + 1]) - static_cast<int64_t>(off[u[t]]);
+                            if (dt < P.light_below) plain |= 1u << t;
+                        }
+                    }
+                }
+            }
         }
     }
     if (!active) return 0.0f;
+    if ((MODE == kEpoch || MODE == kExplicit || MODE == kSequential) && P.plain_neg != 0)
+        plain |= ((2u << KMAX) - 1u) & ~1u;   // every negative slot
     return update_chain<BF16, D, KMAX, MODE == kPersistent, IO>(
         M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates,
-        gl, (MODE == kEpoch || MODE == kExplicit) && P.plain_neg != 0, P.loss != nullptr);
+        gl, plain, P.loss != nullptr);
 }
 
 // Samples of source `src` in epoch P.epoch (kind 0 of the Philox stream), as

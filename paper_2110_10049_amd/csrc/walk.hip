@@ -169,7 +169,8 @@ __device__ __forceinline__ void walk_visit(const WalkTrain& T, int64_t r, int gl
     }
     Elem* M = static_cast<Elem*>(T.emb);
     update_chain<BF16, D, KMAX, false>(M, src, M, src, u, T.k, T.lr, static_cast<uint32_t>(r), T.epoch, T.w2, 7u, 0u,
-                                       T.key0, T.key1, T.updates, gl, T.plain_neg != 0);
+                                       T.key0, T.key1, T.updates, gl,
+                                       T.plain_neg != 0 ? ((2u << KMAX) - 1u) & ~1u : 0u);
 }
 
 // Launch shapes: one wave in rank order (deterministic mode), one rank per

@@ -84,6 +84,7 @@ _SIGNATURES = [
     ("gosh_set_deterministic", C.c_int, [_P, C.c_int]),
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
+    ("gosh_set_plain_light_rows", C.c_int, [_P, C.c_int64]),
     ("gosh_set_loss_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_set_resident_epochs", C.c_int, [_P, C.c_int64]),
     ("gosh_set_lds_levels", C.c_int, [_P, C.c_int64]),
@@ -223,6 +224,10 @@ class Context:
     def set_plain_negatives(self, min_vertices: int):
         """Plain stores for negative rows on levels of at least min_vertices vertices (0 = off)."""
         self.check(self._L.gosh_set_plain_negatives(self.h, min_vertices))
+
+    def set_plain_light_rows(self, min_vertices: int):
+        """Plain stores for rows of at most average degree on levels of at least min_vertices vertices (0 = off)."""
+        self.check(self._L.gosh_set_plain_light_rows(self.h, min_vertices))
 
     def set_resident_epochs(self, max_vertices: int):
         """All epochs of a level of at most max_vertices vertices in one launch (0 = off)."""

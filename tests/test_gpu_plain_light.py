@@ -1,0 +1,95 @@
+"""Rows of at most average degree written with plain stores
+(gosh_set_plain_light_rows; hubs as Section 4.1 defines them keep atomic
+commits) against the atomic write path and the oracle:
+
+* one visit at a time (deterministic mode) a plain store equals the atomic
+  commit, so the rows are bit-identical to the atomic run and match the
+  sequential oracle (Algorithm 3 with Algorithm 1) per row;
+* concurrent epochs at lr = 0 leave every row unchanged and execute the
+  oracle's update count;
+* end to end on the scale-20 workload the AUC stays within 0.01 of the
+  oracle's (test_gpu_e2e.test_config2_auc_matches_oracle, light-row case).
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import init_rows, rmat_csr
+
+pytestmark = pytest.mark.gpu
+SEED = 4
+
+
+def _bf16_bits(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().view(torch.int16).numpy().view(np.uint16)
+
+
+def _rel_rows(a, b):
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+    return float((num / den).max()) if len(a) else 0.0
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("off64", [False, True])
+def test_sequential_plain_light_equals_atomic_and_oracle(gctx, orc, dtype, off64):
+    from paper_2110_10049_amd import gosh as G
+    off, idx = rmat_csr(10, 8, seed=7)      # hubs and light rows, some isolated vertices
+    n, d, k, epochs, lr = len(off) - 1, 128, 3, 3, 0.045
+    print(f"[plain light sequential] {dtype} off64={off64} n={n}", flush=True)
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(off, idx, off64=off64))
+    f = init_rows(n, d, 3)
+    A = torch.from_numpy(f).cuda().to(dtype)
+    B = A.clone()
+    gctx.set_deterministic(True)
+    try:
+        gctx.set_plain_light_rows(1)
+        G.gosh_train(gctx, lv, 0, A, epochs, lr, k)
+        gctx.set_plain_light_rows(0)
+        G.gosh_train(gctx, lv, 0, B, epochs, lr, k)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_light_rows(0)
+        gctx.set_deterministic(False)
+    if dtype == torch.bfloat16:
+        assert np.array_equal(_bf16_bits(A), _bf16_bits(B))
+        bits = orc.f32_to_bf16_rne(f).reshape(n, d)
+        Mo = bits.copy()
+        orc.train(off, idx, Mo, epochs, float(np.float32(lr)), k, SEED, level=0)
+        got, want = orc.bf16_to_f64(_bf16_bits(A)), orc.bf16_to_f64(Mo)
+        assert _rel_rows(got, want) < 2e-2
+        assert np.mean(np.abs(got - want).sum(1) / np.abs(want).sum(1)) < 5e-3
+    else:
+        assert torch.equal(A, B)
+        Mo = f.astype(np.float64)
+        orc.train(off, idx, Mo, epochs, float(np.float32(lr)), k, SEED, level=0)
+        assert _rel_rows(A.cpu().numpy().astype(np.float64), Mo) < 1e-4
+    assert not torch.equal(A.float(), torch.from_numpy(f).cuda())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_concurrent_identity_and_counts(gctx, orc, dtype):
+    from paper_2110_10049_amd import gosh as G
+    off, idx = rmat_csr(12, 16, seed=11)
+    n, d, k, epochs = len(off) - 1, 128, 3, 4
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(off, idx))
+    M0 = torch.from_numpy(init_rows(n, d, 3)).cuda().to(dtype)
+    M = M0.clone()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gctx.set_plain_light_rows(1)
+    try:
+        G.gosh_train(gctx, lv, 0, M, epochs, 0.0, k, 0, cnt)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_light_rows(0)
+    if dtype == torch.bfloat16:
+        assert torch.equal(M.view(torch.int16), M0.view(torch.int16))
+    else:
+        assert torch.equal(M, M0)
+    assert int(cnt.item()) == orc.train(off, idx, np.zeros((n, 8)), epochs, 0.0, k, SEED)
+
+
+def test_plain_light_argument_errors(gctx):
+    from paper_2110_10049_amd import gosh as G
+    with pytest.raises(G.GoshError):
+        gctx.set_plain_light_rows(-1)

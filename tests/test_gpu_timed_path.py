@@ -51,7 +51,8 @@ def _bf16_ulp_apart(a_bits: np.ndarray, b_bits: np.ndarray) -> np.ndarray:
 @pytest.mark.parametrize("off64", [False, True])
 def test_in_kernel_draws_full_scale20(gctx, orc, off64):
     """Every sample k_train draws in one epoch of the scale-20 level 0 (the
-    timed launch: BF16, d = 128, k = 3, plain negatives, lr > 0) equals the
+    timed launch: BF16, d = 128, k = 3, plain negatives and light rows,
+    lr > 0) equals the
     oracle's draw bit for bit."""
     from paper_2110_10049_amd import gosh as G
     sp = train_split(20, 16)
@@ -61,6 +62,7 @@ def test_in_kernel_draws_full_scale20(gctx, orc, off64):
     M = torch.from_numpy(init_rows(n, d, 3)).to(torch.bfloat16).cuda()
     rec = torch.full((n, 1 + k), -7, dtype=torch.int32, device="cuda")
     gctx.set_plain_negatives(65536)
+    gctx.set_plain_light_rows(65536)
     gctx.set_draw_record(rec)
     try:
         G.gosh_train(gctx, lv, 0, M, 1, 0.045, k, 0)
@@ -68,6 +70,7 @@ def test_in_kernel_draws_full_scale20(gctx, orc, off64):
     finally:
         gctx.set_draw_record(None)
         gctx.set_plain_negatives(0)
+        gctx.set_plain_light_rows(0)
     want = orc.draw_all(sp.offsets, sp.indices, SEED, 0, 0, 0, k)
     assert np.array_equal(rec.cpu().numpy(), want)
 

@@ -234,11 +234,13 @@ def test_full_scale20_bench_configuration(gctx, orc):
     M = M0.clone()
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     gctx.set_plain_negatives(65536)
+    gctx.set_plain_light_rows(65536)
     try:
         G.gosh_train(gctx, lv, 0, M, 1, 0.0, k, 0, cnt)
         torch.cuda.synchronize()
     finally:
         gctx.set_plain_negatives(0)
+        gctx.set_plain_light_rows(0)
     assert torch.equal(M.view(torch.int16), M0.view(torch.int16))
     # the update count does not depend on d: the oracle runs with 8-wide rows
     upd = orc.train(sp.offsets, sp.indices, np.zeros((n, 8)), 1, 0.0, k, SEED)
