@@ -1176,10 +1176,12 @@ void free_level(Ctx* c, Level& L) {
     if (L.own_indices) c->free(L.own_indices);
     if (L.map) c->free(L.map);
     if (L.clsz) c->free(L.clsz);
+    if (L.hub_bits) c->free(L.hub_bits);
     L.own_offsets = nullptr;
     L.own_indices = nullptr;
     L.map = nullptr;
     L.clsz = nullptr;
+    L.hub_bits = nullptr;
 }
 
 }  // namespace gosh

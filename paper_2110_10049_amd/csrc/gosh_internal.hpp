@@ -110,6 +110,7 @@ struct Level {
     int32_t* own_indices = nullptr;
     int32_t* map = nullptr;            // map to level+1 (owned), null on the coarsest
     int32_t* clsz = nullptr;           // sizes of level+1's clusters (owned)
+    uint32_t* hub_bits = nullptr;      // bit v set: deg(v) * n > nnz (owned, built on first use)
     int64_t n_deg0 = -1;               // vertices without neighbours (-1: not yet counted)
 };
 

@@ -300,6 +300,41 @@ int lanes_for(int d) {
 }
 int lanes_per_row(gosh_dtype dt, int d) { return dt == GOSH_BF16 ? lanes_for<true>(d) : lanes_for<false>(d); }
 
+// Hub bitmap of a level: bit v of word v / 32 set iff deg(v) >= light_below.
+// One thread per vertex; a wave's 64 flags are one ballot, written by lane 0
+// as two words (waves start at multiples of 64 vertices).
+template <class Off>
+__global__ void k_hub_bits(const Off* off, int64_t n, int64_t light_below, uint32_t* bits) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t v0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; v0 < n; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool hub = v < n && static_cast<int64_t>(off[v + 1]) - static_cast<int64_t>(off[v]) >= light_below;
+        const unsigned long long m = __ballot(hub);
+        if ((threadIdx.x & 63) == 0) {
+            const int64_t w = (v0 + threadIdx.x) >> 5;   // v is a multiple of 64 here
+            if (w * 32 < n) bits[w] = static_cast<uint32_t>(m);
+            if ((w + 1) * 32 < n) bits[w + 1] = static_cast<uint32_t>(m >> 32);
+        }
+    }
+}
+
+const uint32_t* hub_bits(Ctx* c, const Level& L, int64_t light_below) {
+    if (!L.hub_bits) {
+        Level& M = const_cast<Level&>(L);
+        const int64_t words = ceil_div(L.n, 32);
+        M.hub_bits = static_cast<uint32_t*>(c->alloc(sizeof(uint32_t) * static_cast<size_t>(std::max<int64_t>(words, 1))));
+        const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(L.n, 256), 65536));
+        if (L.off64)
+            hipLaunchKernelGGL(k_hub_bits<int64_t>, dim3(blocks), dim3(256), 0, c->stream,
+                               static_cast<const int64_t*>(L.offsets), L.n, light_below, M.hub_bits);
+        else
+            hipLaunchKernelGGL(k_hub_bits<int32_t>, dim3(blocks), dim3(256), 0, c->stream,
+                               static_cast<const int32_t*>(L.offsets), L.n, light_below, M.hub_bits);
+        GOSH_HIP(hipGetLastError());
+    }
+    return L.hub_bits;
+}
+
 TrainParams base_params(Ctx* c, int32_t level, uint32_t tag) {
     TrainParams P{};
     P.key0 = static_cast<uint32_t>(c->seed);
@@ -345,6 +380,7 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     // light rows stored plainly; also in deterministic mode, where one visit
     // at a time makes a plain store equal to the atomic commit
     P.light_below = (c->plain_light_min > 0 && L.n >= c->plain_light_min) ? L.nnz / L.n + 1 : 0;
+    if (P.light_below > 0) P.hub_bits = hub_bits(c, L, P.light_below);
     if (c->record) {
         GOSH_REQUIRE(c->record_cap >= L.n * (1 + k), GOSH_E_INVALID_ARG,
                      "draw record buffer holds fewer than n * (1 + k) entries");

@@ -43,6 +43,7 @@ struct TrainParams {
     // floor(nnz / n) + 1, so light rows are the complement of Section 4.1's
     // hubs (deg * n <= nnz), and hub rows keep their atomic commits
     int64_t light_below;
+    const uint32_t* hub_bits; // with light_below > 0: bit v set iff deg(v) >= light_below
     int32_t* record;          // optional: samples drawn by each visit, [n][1+k]
     double* loss;             // optional: running loss per epoch of the launch (index = epoch - first)
 };
@@ -538,14 +539,15 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
             }
             if constexpr (MODE == kEpoch || MODE == kSequential) {
                 if (P.light_below > 0) {
-                    // light rows are stored plainly; the degree loads run
-                    // beside the row loads of the chain
+                    // light rows are stored plainly; a sample's class comes
+                    // from the level's hub bitmap (n / 8 bytes, cache-resident),
+                    // read beside the row loads of the chain
                     if (deg < P.light_below) plain |= 1u << 31;
 #pragma unroll
                     for (int t = 0; t <= KMAX; ++t) {
                         if (t <= k && u[t] >= 0) {
-                            const int64_t dt = static_cast<int64_t>(off[u[t] + 1]) - static_cast<int64_t>(off[u[t]]);
-                            if (dt < P.light_below) plain |= 1u << t;
+                            const uint32_t w = P.hub_bits[static_cast<uint32_t>(u[t]) >> 5];
+                            if (((w >> (static_cast<uint32_t>(u[t]) & 31u)) & 1u) == 0u) plain |= 1u << t;
                         }
                     }
                 }
