@@ -236,3 +236,29 @@ def test_hogwild_trainer_one_thread_is_sequential(orc):
     assert u1 == u2 == u3
     assert np.array_equal(A, B)
     assert np.all(np.isfinite(C)) and np.abs(C - A).max() < 0.05
+
+
+@pytest.mark.parametrize("a", [0.0, 0.7, 2.5])
+def test_running_loss_closed_form(orc, a):
+    # lr = 0 and every row a * e_1: every update reads the dot a^2, so an
+    # epoch's running loss (Section 2's objective over its executed updates)
+    # is P log(1 + e^-a^2) + N log(1 + e^a^2), P and N its executed positive
+    # and negative updates; the rows never change
+    off, idx = rmat_csr(8, 4, seed=9)          # some vertices without neighbours
+    n, d, k, epochs = len(off) - 1, 8, 3, 3
+    M = np.zeros((n, d))
+    M[:, 0] = a
+    M0 = M.copy()
+    u, loss = orc.train_loss(off, idx, M, epochs, 0.0, k, 4, level=2, tag=1)
+    assert np.array_equal(M, M0)
+    x = a * a
+    total = 0
+    for ep in range(epochs):
+        dr = orc.draw_all(off, idx, 4, 2, 1, ep, k)
+        src = np.arange(n)[:, None]
+        P = int((dr[:, 0] >= 0).sum())
+        N = int(((dr[:, 1:] >= 0) & (dr[:, 1:] != src)).sum())
+        want = P * math.log1p(math.exp(-x)) + N * math.log1p(math.exp(x))
+        assert loss[ep] == pytest.approx(want, rel=1e-12)
+        total += P + N
+    assert u == total
