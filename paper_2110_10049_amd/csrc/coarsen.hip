@@ -423,91 +423,130 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // One wave per small segment: its clusters OR-ed into the wave's bitmap over
-// the next level's vertex ids (W 32-bit words of dynamic LDS, only the words
-// between the segment's smallest and largest id cleared and scanned), then
-// the distinct ids written back in place, ascending (bit order), each lane
-// placing its word's ids after a wave prefix sum of the popcounts;
-// cnt[c] = their number.
+// the next level's vertex ids (W 32-bit words of dynamic LDS, cleared once
+// per wave), then the distinct ids written back in place, ascending (bit
+// order), and exactly the words that were set cleared again; cnt[c] = their
+// number.  A segment with at least W / 2 entries (dense coarse levels) reads
+// all W words back 64 at a time, each lane placing its word's ids after a
+// wave prefix sum of the popcounts.  A shorter one (level 0: a few hundred
+// entries against thousands of words) also marks a summary with one bit per
+// bitmap word (S = ceil(W / 32) words after the bitmap), and lane l reads
+// back only the marked words of its summary words [l q, l q + q), so the
+// segment costs its entries, not the words of the bitmap.
 __global__ __launch_bounds__(64 * kSegWaves) void k_dedup_small(const int64_t* segstart, int64_t n_next, int W,
                                                                 uint32_t* raw, int32_t* cnt) {
     extern __shared__ uint32_t seg_bitmaps[];
     const int lane = threadIdx.x & 63;
-    uint32_t* bm = seg_bitmaps + static_cast<int64_t>(threadIdx.x >> 6) * W;
+    const int S = (W + 31) >> 5;
+    const int q = (S + 63) >> 6;
+    uint32_t* bm = seg_bitmaps + static_cast<int64_t>(threadIdx.x >> 6) * (W + S);
+    uint32_t* sm = bm + W;
+    for (int w = lane; w < W + S; w += 64) bm[w] = 0u;
+    wave_lds_sync();
     const int64_t nw = static_cast<int64_t>(gridDim.x) * kSegWaves;
     for (int64_t c = static_cast<int64_t>(blockIdx.x) * kSegWaves + (threadIdx.x >> 6); c < n_next; c += nw) {
         const int64_t s0 = segstart[c];
         const int64_t len = segstart[c + 1] - s0;
-        if (len > kSegSmall) continue;   // a big segment: sorted with the others
-        uint32_t kmin = kSegSent, kmax = 0;
+        if (len > kSegSmall) continue;   // a hub cluster: chunked with the others
+        const bool sparse = static_cast<int64_t>(W) > 2 * len;   // wave-uniform
+        const int w0 = 0, w1 = W - 1;
         for (int64_t i = lane; i < len; i += 64) {
             const uint32_t x = raw[s0 + i];
             if (x != kSegSent) {
-                kmin = min(kmin, x);
-                kmax = max(kmax, x);
+                atomicOr(&bm[x >> 5], 1u << (x & 31u));
+                if (sparse) atomicOr(&sm[x >> 10], 1u << ((x >> 5) & 31u));
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            kmin = min(kmin, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmin), o, 64)));
-            kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), o, 64)));
-        }
-        if (kmin > kmax) {   // no entry leaves the cluster
-            if (lane == 0) cnt[c] = 0;
-            continue;
-        }
-        const int w0 = static_cast<int>(kmin >> 5), w1 = static_cast<int>(kmax >> 5);
-        for (int w = w0 + lane; w <= w1; w += 64) bm[w] = 0u;
         wave_lds_sync();
-        for (int64_t i = lane; i < len; i += 64) {
-            const uint32_t x = raw[s0 + i];
-            if (x != kSegSent) atomicOr(&bm[x >> 5], 1u << (x & 31u));
-        }
-        wave_lds_sync();
-        int64_t total = 0;
-        for (int base = w0; base <= w1; base += 64) {
-            const int w = base + lane;
-            uint32_t word = w <= w1 ? bm[w] : 0u;
-            const int pc = __popc(word);
+        int total = 0;
+        if (!sparse) {
+            for (int base = w0; base <= w1; base += 64) {
+                const int w = base + lane;
+                uint32_t word = w <= w1 ? bm[w] : 0u;
+                const int pc = __popc(word);
+                int incl = pc;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += t;
+                }
+                int64_t pos = s0 + total + (incl - pc);
+                if (w <= w1) bm[w] = 0u;
+                while (word) {
+                    const int bit = __ffs(word) - 1;
+                    raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
+                    word &= word - 1u;
+                }
+                total += __shfl(incl, 63, 64);
+            }
+        } else {
+            int pc = 0;
+            for (int j = 0; j < q; ++j) {
+                const int sidx = lane * q + j;
+                if (sidx < S) {
+                    uint32_t sw = sm[sidx];
+                    while (sw) {
+                        const int b = __ffs(sw) - 1;
+                        pc += __popc(bm[(sidx << 5) + b]);
+                        sw &= sw - 1u;
+                    }
+                }
+            }
             int incl = pc;
             for (int o = 1; o < 64; o <<= 1) {
                 const int t = __shfl_up(incl, o, 64);
                 if (lane >= o) incl += t;
             }
-            int64_t pos = s0 + total + (incl - pc);
-            while (word) {
-                const int bit = __ffs(word) - 1;
-                raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
-                word &= word - 1u;
+            total = __shfl(incl, 63, 64);
+            int64_t pos = s0 + (incl - pc);
+            for (int j = 0; j < q; ++j) {
+                const int sidx = lane * q + j;
+                if (sidx < S) {
+                    uint32_t sw = sm[sidx];
+                    while (sw) {
+                        const int w = (sidx << 5) + __ffs(sw) - 1;
+                        uint32_t word = bm[w];
+                        while (word) {
+                            const int bit = __ffs(word) - 1;
+                            raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
+                            word &= word - 1u;
+                        }
+                        bm[w] = 0u;
+                        sw &= sw - 1u;
+                    }
+                    sm[sidx] = 0u;
+                }
             }
-            total += __shfl(incl, 63, 64);
         }
-        if (lane == 0) cnt[c] = static_cast<int32_t>(total);
+        if (lane == 0) cnt[c] = total;
         wave_lds_sync();
     }
 }
 
 // Segments longer than kSegSmall ("giant": hub clusters) are cut into chunks
-// of kGiantChunk entries: cc[c] = chunks of cluster c (0 if not giant),
-// gf[c] = 1 for a giant.
-__global__ void k_giant_flags(const int64_t* segstart, int64_t n_next, int32_t* gf, int32_t* cc) {
+// of kGiantChunk entries.  pk[c] = gf + (chunks << 32), gf = 1 for a giant
+// and chunks its chunk count (0 if not giant): one exclusive scan of pk gives
+// a giant's index among the giants in the low half (at most n_next < 2^31, so
+// it never carries) and its first chunk in the high half.
+__global__ void k_giant_flags(const int64_t* segstart, int64_t n_next, int64_t* pk) {
     GRID_STRIDE(c, n_next) {
         const int64_t len = segstart[c + 1] - segstart[c];
-        const bool g = len > kSegSmall;
-        gf[c] = g ? 1 : 0;
-        cc[c] = g ? static_cast<int32_t>(ceil_div(len, kGiantChunk)) : 0;
+        pk[c] = len > kSegSmall ? 1 + (ceil_div(len, kGiantChunk) << 32) : 0;
     }
 }
+__device__ __forceinline__ int64_t giant_index(int64_t pre) { return pre & 0xFFFFFFFFll; }
+__device__ __forceinline__ int64_t first_chunk(int64_t pre) { return pre >> 32; }
 
 constexpr int kGiantThreads = 1024;
 
 // One workgroup per chunk of a giant segment: the chunk's clusters OR-ed
 // into the workgroup's LDS bitmap, then its non-zero words OR-ed into the
-// giant's global bitmap gbm[gidx[c] * W ..].  Chunk t belongs to the last
-// cluster c with cpos[c] <= t (cpos: exclusive prefix of cc; clusters without
-// chunks share their start with the next cluster, so the last one is a giant).
+// giant's global bitmap (row giant_index(pre[c]) of gbm, W words).  Chunk t
+// belongs to the last cluster c whose first chunk is <= t (clusters without
+// chunks share their first chunk with the next cluster, so the last one is a
+// giant).
 __global__ __launch_bounds__(kGiantThreads) void k_giant_chunks(const int64_t* segstart, int64_t n_next,
-                                                                const int64_t* cpos, int64_t chunks,
-                                                                const int64_t* gidx, int W, const uint32_t* raw,
-                                                                uint32_t* gbm) {
+                                                                const int64_t* pre, int64_t chunks, int W,
+                                                                const uint32_t* raw, uint32_t* gbm) {
     extern __shared__ uint32_t seg_bitmaps[];
     __shared__ uint32_t red[2][kGiantThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -515,11 +554,11 @@ __global__ __launch_bounds__(kGiantThreads) void k_giant_chunks(const int64_t* s
         int64_t lo = 0, hi = n_next;
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
-            if (cpos[mid] <= t) lo = mid;
+            if (first_chunk(pre[mid]) <= t) lo = mid;
             else hi = mid;
         }
         const int64_t cl = lo;
-        const int64_t s0 = segstart[cl] + (t - cpos[cl]) * kGiantChunk;
+        const int64_t s0 = segstart[cl] + (t - first_chunk(pre[cl])) * kGiantChunk;
         const int64_t len = min(static_cast<int64_t>(kGiantChunk), segstart[cl + 1] - s0);
         uint32_t kmin = kSegSent, kmax = 0;
         for (int64_t i = threadIdx.x; i < len; i += kGiantThreads) {
@@ -553,7 +592,7 @@ __global__ __launch_bounds__(kGiantThreads) void k_giant_chunks(const int64_t* s
                 if (x != kSegSent) atomicOr(&seg_bitmaps[x >> 5], 1u << (x & 31u));
             }
             __syncthreads();
-            uint32_t* g = gbm + gidx[cl] * static_cast<int64_t>(W);
+            uint32_t* g = gbm + giant_index(pre[cl]) * static_cast<int64_t>(W);
             for (int w = w0 + static_cast<int>(threadIdx.x); w <= w1; w += kGiantThreads) {
                 const uint32_t word = seg_bitmaps[w];
                 if (word) atomicOr(&g[w], word);
@@ -611,10 +650,10 @@ __global__ __launch_bounds__(kGiantThreads) void k_giant_emit(const int32_t* gc,
     }
 }
 
-// gc[gidx[c]] = c for every giant
-__global__ void k_giant_list(const int32_t* gf, const int64_t* gidx, int64_t n_next, int32_t* gc) {
+// gc[giant index of c] = c for every giant
+__global__ void k_giant_list(const int64_t* segstart, const int64_t* pre, int64_t n_next, int32_t* gc) {
     GRID_STRIDE(c, n_next) {
-        if (gf[c]) gc[gidx[c]] = static_cast<int32_t>(c);
+        if (segstart[c + 1] - segstart[c] > kSegSmall) gc[giant_index(pre[c])] = static_cast<int32_t>(c);
     }
 }
 
@@ -807,43 +846,48 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
     mem.reset();
     ckey.reset();
 
-    // giant segments: chunk count and list
-    DevBuf<int32_t> gf(c, n_next), cc(c, n_next);
-    DevBuf<int64_t> gidx(c, n_next), cpos(c, n_next);
-    hipLaunchKernelGGL(k_giant_flags, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, n_next, gf.p, cc.p);
+    // giant segments: their count and chunks from one packed scan
+    DevBuf<int64_t> pre(c, n_next);
+    hipLaunchKernelGGL(k_giant_flags, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, n_next, pre.p);
     GOSH_HIP(hipGetLastError());
-    int64_t G = 0, chunks = 0;
-    scan_i32_to_i64(c, gf.p, gidx.p, n_next, &G);
-    scan_i32_to_i64(c, cc.p, cpos.p, n_next, &chunks);
-    cc.reset();
+    int64_t packed = 0;
+    scan_i64(c, pre.p, pre.p, n_next, false, ScanOp::Sum, &packed);
+    const int64_t G = packed & 0xFFFFFFFFll, chunks = packed >> 32;
 
     DevBuf<int32_t> cnt(c, n_next);
-    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(W) * kSegWaves;
+    // as many workgroups as fit on the device at once: each wave clears its
+    // bitmap once and then takes segment after segment
+    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(W + ceil_div(W, 32)) * kSegWaves;
     GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dedup_small),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    hipLaunchKernelGGL(k_dedup_small, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(n_next, kSegWaves), 8192))),
+    int per_cu = 0, cus = 0;
+    GOSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_dedup_small),
+                                                          64 * kSegWaves, lds));
+    GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int64_t dblocks = std::min<int64_t>(ceil_div(n_next, kSegWaves),
+                                              static_cast<int64_t>(std::max(per_cu, 1)) * std::max(cus, 1));
+    hipLaunchKernelGGL(k_dedup_small, dim3(static_cast<unsigned>(std::max<int64_t>(dblocks, 1))),
                        dim3(64 * kSegWaves), lds, c->stream, segstart.p, n_next, static_cast<int>(W), raw.p, cnt.p);
     GOSH_HIP(hipGetLastError());
     DevBuf<int32_t> gc(c, std::max<int64_t>(G, 1));
     DevBuf<uint32_t> gbm(c, std::max<int64_t>(G * W, 1));
     if (G > 0) {
         GOSH_HIP(hipMemsetAsync(gbm.p, 0, sizeof(uint32_t) * G * W, c->stream));
-        hipLaunchKernelGGL(k_giant_list, grid_for(n_next), dim3(kThreads), 0, c->stream, gf.p, gidx.p, n_next, gc.p);
+        hipLaunchKernelGGL(k_giant_list, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, pre.p, n_next,
+                           gc.p);
         GOSH_HIP(hipGetLastError());
         const size_t glds = sizeof(uint32_t) * static_cast<size_t>(W);
         GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_giant_chunks),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(glds)));
         hipLaunchKernelGGL(k_giant_chunks, dim3(static_cast<unsigned>(std::min<int64_t>(chunks, 65536))),
-                           dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, cpos.p, chunks, gidx.p,
+                           dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, pre.p, chunks,
                            static_cast<int>(W), raw.p, gbm.p);
         GOSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_giant_emit, dim3(static_cast<unsigned>(std::min<int64_t>(G, 4096))), dim3(kGiantThreads), 0,
                            c->stream, gc.p, G, static_cast<int>(W), gbm.p, cnt.p, nullptr, nullptr);
         GOSH_HIP(hipGetLastError());
     }
-    gidx.reset();
-    cpos.reset();
-    gf.reset();
+    pre.reset();
 
     // offsets from the distinct counts, then the rows
     DevBuf<int64_t> offs(c, n_next);
