@@ -39,6 +39,8 @@ def lib():
             build()
         L = C.CDLL(_LIB_PATH)
         L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_philox_many.argtypes = [_u32p, C.c_int64, _u32p, _u32p]
+        L.orc_philox_many.restype = None
         L.orc_stream_block.argtypes = [C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int64,
                                        C.c_uint32, C.c_uint32, C.c_uint32, _u32p]
         L.orc_draw_samples.argtypes = [_i64p, _i32p, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32,
@@ -120,6 +122,14 @@ def _csr(offsets, indices):
 def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def philox_many(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of every row of ctr ([m, 4] uint32) under one key: [m, 4]."""
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    out = np.zeros_like(ctr)
+    lib().orc_philox_many(ctr.reshape(-1), len(ctr), np.asarray(key, np.uint32), out.reshape(-1))
     return out
 
 
@@ -329,13 +339,17 @@ def unit_epochs(sched, graphs, unit="passes"):
 
 
 def gosh_embed(offsets, indices, init_fn, d, e, p, lr, k, seed, threshold=100,
-               ratio=0.8, bf16=False, tag=0, levels=None, epoch_unit="passes", losses=None):
+               ratio=0.8, bf16=False, tag=0, levels=None, epoch_unit="passes", losses=None,
+               prolong_fn=None, keep=None):
     """Algorithm 2: coarsen, initialise the coarsest rows with
     ``init_fn(n_coarsest, d)`` (float32), train levels D-1 .. 0 with their
     epoch share (in the given epoch unit, see unit_epochs), expanding each
     trained level to the next finer one.  Returns (M_0, info) with M_0
     float64 or BF16 bits.  With a dict `losses`, losses[i] receives level
-    i's per-epoch running loss (train_loss)."""
+    i's per-epoch running loss (train_loss).  prolong_fn(M, i, graphs,
+    maps) expands trained level i+1 onto level i in place of the copy, in
+    the rows' storage (FP64, or BF16 bits); a dict `keep` receives every
+    level's trained rows."""
     if levels is None:
         graphs, maps = coarsen_levels(offsets, indices, threshold, ratio)
     else:
@@ -352,8 +366,13 @@ def gosh_embed(offsets, indices, init_fn, d, e, p, lr, k, seed, threshold=100,
             updates.append(u)
         else:
             updates.append(train(off, idx, M, int(sched[i]), lr, k, seed, level=i, tag=tag))
+        if keep is not None:
+            keep[i] = M.copy()
         if i > 0:
-            M = prolong(M, maps[i - 1])
+            if prolong_fn is not None:
+                M = np.ascontiguousarray(prolong_fn(M, i - 1, graphs, maps), dtype=M.dtype)
+            else:
+                M = prolong(M, maps[i - 1])
     return M, {"levels": D, "schedule": sched, "sizes": [len(g[0]) - 1 for g in graphs],
                "updates": updates[::-1]}
 

@@ -70,6 +70,13 @@ void orc_stream_block(uint64_t seed, int32_t level, uint32_t tag, int32_t epoch,
     orc_philox4x32_10(ctr, key, out);
 }
 
+/* m independent Philox blocks: out[4i..4i+3] = philox(ctr[4i..4i+3], key). */
+void orc_philox_many(const uint32_t *ctr, int64_t m, const uint32_t key[2], uint32_t *out)
+{
+    for (int64_t i = 0; i < m; ++i)
+        orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 /* floor(r * N / 2^32): maps a uniform 32-bit word onto [0, N). */
 static int64_t scale_word(uint32_t r, int64_t N)
 {

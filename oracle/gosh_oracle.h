@@ -28,6 +28,8 @@ extern "C" {
 
 /* Philox4x32 with 10 rounds: out = philox(ctr, key). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* m blocks at once: ctr and out hold m consecutive 4-word groups. */
+void orc_philox_many(const uint32_t *ctr, int64_t m, const uint32_t key[2], uint32_t *out);
 
 /* One 128-bit block of the method's random stream.  Counter layout:
  *   ctr = (src, epoch, (level & 0xFF) | tag << 8, kind << 24 | slot << 16 | block)

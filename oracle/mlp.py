@@ -116,3 +116,74 @@ def init_params(d, H, seed, w2_zero=True):
     b1 = np.zeros(H)
     W2 = np.zeros((d, H)) if w2_zero else rng.uniform(-1 / math.sqrt(H), 1 / math.sqrt(H), size=(d, H))
     return Params(W1, b1, W2, np.zeros(d))
+
+
+# --------------------------------------------------------------------------- training on level pairs
+def init_params_stream(d, H, seed):
+    """The network's starting point as drawn from the counter-based stream
+    (Philox4x32-10, Salmon et al. 2011) keyed by the 64-bit seed: element p
+    of W1 (row-major, H x (d+2)) takes word 0 of the block with counter
+    (p mod 2^32, p div 2^32, 0, kind 3 << 24), u = (word >> 8) / 2^24, and
+    W1[p] = lim (2 u - 1), lim = 1/sqrt(d+2), evaluated in float32; b1, W2
+    and b2 are zero (copy prolongation)."""
+    from . import philox_many
+    F = d + 2
+    n = H * F
+    p = np.arange(n, dtype=np.uint64)
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = (p & 0xFFFFFFFF).astype(np.uint32)
+    ctr[:, 1] = (p >> np.uint64(32)).astype(np.uint32)
+    ctr[:, 3] = np.uint32(3 << 24)
+    r = philox_many(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    lim = np.float32(1.0 / math.sqrt(F))
+    u = (r[:, 0] >> np.uint32(8)).astype(np.float32) * np.float32(1.0 / 16777216.0)
+    w = lim * (np.float32(2.0) * u - np.float32(1.0))
+    return Params(w.astype(np.float64).reshape(H, F), np.zeros(H), np.zeros((d, H)), np.zeros(d))
+
+
+def minibatch(step, batch, total, seed, tag):
+    """Pair indices of one minibatch, drawn uniformly with replacement from
+    the stream: row b takes the block with counter (b, step, tag << 8,
+    kind 2 << 24) and index ((word0 << 32 | word1) >> 16) mod total."""
+    from . import philox_many
+    ctr = np.zeros((batch, 4), np.uint32)
+    ctr[:, 0] = np.arange(batch, dtype=np.uint32)
+    ctr[:, 1] = np.uint32(step)
+    ctr[:, 2] = np.uint32((tag << 8) & 0xFFFFFFFF)
+    ctr[:, 3] = np.uint32(2 << 24)
+    r = philox_many(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)).astype(np.uint64)
+    return (((r[:, 0] << np.uint64(32)) | r[:, 1]) >> np.uint64(16)) % np.uint64(total)
+
+
+def level_pairs(coarse, fine, mp, deg):
+    """Training pairs of one fine level: for every fine vertex v the coarse
+    row of its super vertex c = mp[v], the trained fine row, deg(v) and the
+    size of cluster c."""
+    mp = np.asarray(mp, np.int64)
+    clsz = np.bincount(mp, minlength=len(coarse))
+    return (np.asarray(coarse, np.float64)[mp], np.asarray(fine, np.float64), np.asarray(deg, np.int64), clsz[mp])
+
+
+def train_pairs(P: Params, sources, steps, batch, lr, seed, tag, S: AdamState | None = None):
+    """Adam on the MSE of minibatches drawn over the concatenated pairs of
+    `sources` (level_pairs tuples, in order).  Returns the loss of every
+    step before its update."""
+    C = np.concatenate([s[0] for s in sources])
+    T = np.concatenate([s[1] for s in sources])
+    deg = np.concatenate([s[2] for s in sources])
+    cl = np.concatenate([s[3] for s in sources])
+    S = S or adam_init(P)
+    losses = []
+    for step in range(steps):
+        u = minibatch(step, batch, len(C), seed, tag).astype(np.int64)
+        Y, cache = forward(P, features(C[u], deg[u], cl[u]), C[u])
+        losses.append(mse(Y, T[u]))
+        adam_step(P, backward(P, Y, T[u], cache), S, lr)
+    return np.array(losses)
+
+
+def prolong_learned(P: Params, coarse, mp, deg):
+    """Learned ExpandEmbedding: the fine row of every vertex v of the finer
+    level from its super vertex's coarse row."""
+    C, _, dg, cl = level_pairs(coarse, np.zeros((len(mp), np.asarray(coarse).shape[1])), mp, deg)
+    return forward(P, features(C, dg, cl), C)[0]

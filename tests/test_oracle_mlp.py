@@ -139,3 +139,54 @@ def test_training_reduces_mse():
         Y, cache = mlp.forward(P, X, C)
         mlp.adam_step(P, mlp.backward(P, Y, T, cache), S, 1e-2)
     assert mlp.mse(mlp.forward(P, X, C)[0], T) < 0.1 * first
+
+
+def test_stream_init_is_uniform_copy_start():
+    # W1 uniform on [-1/sqrt(d+2), 1/sqrt(d+2)] (mean 0, variance lim^2 / 3),
+    # everything else zero, so the network starts as copy prolongation
+    d, H = 64, 128
+    P = mlp.init_params_stream(d, H, 4)
+    lim = 1.0 / np.sqrt(d + 2)
+    w = P.W1.ravel()
+    assert np.all(np.abs(w) <= lim) and w.min() < -0.99 * lim and w.max() > 0.99 * lim
+    assert abs(w.mean()) < 4 * lim / np.sqrt(3 * w.size)
+    assert abs(w.var() / (lim * lim / 3) - 1) < 0.05
+    assert not P.W2.any() and not P.b1.any() and not P.b2.any()
+    assert np.array_equal(mlp.init_params_stream(d, H, 4).W1, P.W1)
+    assert not np.array_equal(mlp.init_params_stream(d, H, 5).W1, P.W1)
+
+
+def test_minibatch_uniform_over_pairs():
+    total, batch = 97, 4096
+    counts = np.zeros(total)
+    for step in range(10):
+        u = mlp.minibatch(step, batch, total, 4, 3)
+        assert u.min() >= 0 and u.max() < total
+        counts += np.bincount(u.astype(np.int64), minlength=total)
+    exp = 10 * batch / total
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    assert chi2 < 160            # 96 degrees of freedom; p < 1e-5 above
+    assert not np.array_equal(mlp.minibatch(0, 64, total, 4, 3), mlp.minibatch(1, 64, total, 4, 3))
+    assert not np.array_equal(mlp.minibatch(0, 64, total, 4, 3), mlp.minibatch(0, 64, total, 4, 4))
+
+
+def test_train_pairs_learns_and_lr_zero_keeps():
+    rng = np.random.default_rng(2)
+    d, H, nc, nf = 32, 64, 50, 400
+    coarse = rng.normal(size=(nc, d)) * 0.3
+    mp = rng.integers(0, nc, size=nf)
+    deg = rng.integers(1, 60, size=nf)
+    fine = coarse[mp] + 0.05 * np.log1p(deg)[:, None]
+    src = [mlp.level_pairs(coarse, fine, mp, deg)]
+    P0 = mlp.init_params_stream(d, H, 4)
+    P = P0.copy()
+    mlp.train_pairs(P, src, 5, 64, 0.0, 4, 1)
+    assert np.array_equal(P.W1, P0.W1) and not P.W2.any()
+    losses = mlp.train_pairs(P, src, 300, 128, 3e-3, 4, 1)
+    assert losses[-10:].mean() < 0.1 * losses[:10].mean()
+    # W2 = 0: learned prolongation is the copy
+    assert np.array_equal(mlp.prolong_learned(P0, coarse, mp, deg), coarse[mp])
+    # the trained network moves every fine row toward its target
+    err_l = np.mean((mlp.prolong_learned(P, coarse, mp, deg) - fine) ** 2)
+    err_c = np.mean((coarse[mp] - fine) ** 2)
+    assert err_l < 0.2 * err_c
