@@ -608,6 +608,7 @@ def walk_workload(a):
     calibration_copy(a.copy_calibration_mib)
     ctx = G.Context(0, seed=seeds["philox"])
     ctx.set_plain_negatives(a.plain_neg_min)
+    ctx.set_plain_light_rows(a.plain_light_min)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     G.gosh_validate_csr(ctx, g, check_symmetry=True)
     cfg = EmbedConfig(d=d, epochs=E, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=threshold,

@@ -183,7 +183,8 @@ gosh_status gosh_set_lds_levels(gosh_ctx* ctx, int64_t max_vertices);
 gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices);
 
 /* Write discipline by degree (Section 3.1's lock-free sources; Section 4.1's
- * hub definition).  With min_vertices > 0, gosh_train writes every row of
+ * hub definition).  With min_vertices > 0, gosh_train and gosh_train_walks
+ * write every row of
  * degree at most the level's average (deg * n <= nnz: not a hub) with plain
  * stores of the new value -- the source, the positive and the negatives
  * alike -- on levels of at least min_vertices vertices, and keeps the atomic

@@ -164,6 +164,8 @@ void validate_csr(Ctx* c, const gosh_csr* g, bool symmetry);
 void coarsen(Ctx* c, const gosh_csr* g0, int64_t threshold, double ratio, gosh_levels* out);
 int64_t count_isolated(Ctx* c, const Level& L);           // cached in L
 const int32_t* cluster_sizes(Ctx* c, const Level& L, int64_t n_next);  // computed on first use
+// bit v set iff deg(v) >= light_below (built on first use, kept with the level)
+const uint32_t* hub_bits(Ctx* c, const Level& L, int64_t light_below);
 void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d,
                  int epochs, float lr, int k, uint32_t tag, uint64_t* updates_dev);
 void draw_samples(Ctx* c, const Level& L, int32_t level, int32_t epoch, int k, uint32_t tag,

@@ -318,6 +318,16 @@ __global__ void k_hub_bits(const Off* off, int64_t n, int64_t light_below, uint3
     }
 }
 
+TrainParams base_params(Ctx* c, int32_t level, uint32_t tag) {
+    TrainParams P{};
+    P.key0 = static_cast<uint32_t>(c->seed);
+    P.key1 = static_cast<uint32_t>(c->seed >> 32);
+    P.w2 = stream_word2(level, tag);
+    return P;
+}
+
+}  // namespace
+
 const uint32_t* hub_bits(Ctx* c, const Level& L, int64_t light_below) {
     if (!L.hub_bits) {
         Level& M = const_cast<Level&>(L);
@@ -334,16 +344,6 @@ const uint32_t* hub_bits(Ctx* c, const Level& L, int64_t light_below) {
     }
     return L.hub_bits;
 }
-
-TrainParams base_params(Ctx* c, int32_t level, uint32_t tag) {
-    TrainParams P{};
-    P.key0 = static_cast<uint32_t>(c->seed);
-    P.key1 = static_cast<uint32_t>(c->seed >> 32);
-    P.w2 = stream_word2(level, tag);
-    return P;
-}
-
-}  // namespace
 
 void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d, int epochs,
                  float lr, int k, uint32_t tag, uint64_t* updates_dev) {

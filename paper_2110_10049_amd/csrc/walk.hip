@@ -137,6 +137,10 @@ struct WalkTrain {
     uint32_t key0, key1, epoch, w2;
     unsigned long long* updates;
     int32_t plain_neg;        // negatives written with plain stores
+    // with light_below > 0, rows of degree below it (source, positive and
+    // negatives) are written with plain stores; hub_bits marks the others
+    int64_t light_below;
+    const uint32_t* hub_bits;
 };
 
 template <bool BF16, int D, int KMAX>
@@ -167,10 +171,19 @@ __device__ __forceinline__ void walk_visit(const WalkTrain& T, int64_t r, int gl
 #pragma unroll
         for (int t = 1; t <= KMAX; ++t) u[t] = (t <= T.k) ? static_cast<int32_t>(scale_u32(wd[t], T.n)) : -1;
     }
+    uint32_t plain = T.plain_neg != 0 ? ((2u << KMAX) - 1u) & ~1u : 0u;
+    if (T.light_below > 0) {
+        const auto light = [&](int32_t x) {
+            return ((T.hub_bits[static_cast<uint32_t>(x) >> 5] >> (static_cast<uint32_t>(x) & 31u)) & 1u) == 0u;
+        };
+        if (light(src)) plain |= 1u << 31;
+#pragma unroll
+        for (int t = 0; t <= KMAX; ++t)
+            if (t <= T.k && u[t] >= 0 && light(u[t])) plain |= 1u << t;
+    }
     Elem* M = static_cast<Elem*>(T.emb);
     update_chain<BF16, D, KMAX, false>(M, src, M, src, u, T.k, T.lr, static_cast<uint32_t>(r), T.epoch, T.w2, 7u, 0u,
-                                       T.key0, T.key1, T.updates, gl,
-                                       T.plain_neg != 0 ? ((2u << KMAX) - 1u) & ~1u : 0u);
+                                       T.key0, T.key1, T.updates, gl, plain);
 }
 
 // Launch shapes: one wave in rank order (deterministic mode), one rank per
@@ -358,6 +371,9 @@ void train_walks(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     T.w2 = W.A.w2;
     T.updates = W.A.updates;
     T.plain_neg = (!c->deterministic && c->plain_neg_min > 0 && L.n >= c->plain_neg_min) ? 1 : 0;
+    // light rows stored plainly (also in deterministic mode, where it changes no bit)
+    T.light_below = (c->plain_light_min > 0 && L.n >= c->plain_light_min) ? L.nnz / L.n + 1 : 0;
+    if (T.light_below > 0) T.hub_bits = hub_bits(c, L, T.light_below);
     // optional timing: events before the sampling, between sampling and
     // training, and after the training of every epoch
     std::vector<hipEvent_t> ev;

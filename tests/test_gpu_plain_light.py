@@ -7,6 +7,8 @@ commits) against the atomic write path and the oracle:
   sequential oracle (Algorithm 3 with Algorithm 1) per row;
 * concurrent epochs at lr = 0 leave every row unchanged and execute the
   oracle's update count;
+* the random-walk trainer likewise (bit identity with the atomic path one
+  pair at a time, and the sequential reference per row);
 * end to end on the scale-20 workload the AUC stays within 0.01 of the
   oracle's (test_gpu_e2e.test_config2_auc_matches_oracle, light-row case).
 """
@@ -93,3 +95,39 @@ def test_plain_light_argument_errors(gctx):
     from paper_2110_10049_amd import gosh as G
     with pytest.raises(G.GoshError):
         gctx.set_plain_light_rows(-1)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_walk_trainer_plain_light_equals_atomic_and_oracle(gctx, orc, dtype):
+    # the random-walk trainer (Section 3.2) with light rows stored plainly:
+    # one pair at a time it equals the atomic path bit for bit and the
+    # sequential reference per row
+    from paper_2110_10049_amd import gosh as G
+    off, idx = rmat_csr(10, 8, seed=7)
+    n, d, k, epochs, lr, length, window = len(off) - 1, 64, 3, 2, 0.045, 5, 2
+    lv = G.gosh_levels_single(gctx, G.CSR.from_numpy(off, idx))
+    f = init_rows(n, d, 3) * 8
+    A = torch.from_numpy(f).cuda().to(dtype)
+    B = A.clone()
+    gctx.set_deterministic(True)
+    try:
+        gctx.set_plain_light_rows(1)
+        G.gosh_train_walks(gctx, lv, 0, A, epochs, lr, k, length, window)
+        gctx.set_plain_light_rows(0)
+        G.gosh_train_walks(gctx, lv, 0, B, epochs, lr, k, length, window)
+        torch.cuda.synchronize()
+    finally:
+        gctx.set_plain_light_rows(0)
+        gctx.set_deterministic(False)
+    if dtype == torch.bfloat16:
+        assert np.array_equal(_bf16_bits(A), _bf16_bits(B))
+        bits = orc.f32_to_bf16_rne(f).reshape(n, d)
+        Mo = bits.copy()
+        orc.train_walks(off, idx, Mo, epochs, float(np.float32(lr)), k, length, window, SEED)
+        got, want = orc.bf16_to_f64(_bf16_bits(A)), orc.bf16_to_f64(Mo)
+        assert _rel_rows(got, want) < 2e-2
+    else:
+        assert torch.equal(A, B)
+        Mo = f.astype(np.float64)
+        orc.train_walks(off, idx, Mo, epochs, float(np.float32(lr)), k, length, window, SEED)
+        assert _rel_rows(A.cpu().numpy().astype(np.float64), Mo) < 1e-4
