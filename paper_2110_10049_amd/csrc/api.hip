@@ -159,6 +159,8 @@ gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream, uint64_
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->scratch = c->alloc(4096);
         GOSH_HIP(hipMemsetAsync(c->scratch, 0, 4096, c->stream));
+        GOSH_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sizeof(int64_t) * Ctx::kPinnedSlots,
+                               hipHostMallocDefault));
         gosh::batched_noalloc_init(device);
     });
     if (st != GOSH_OK) {
@@ -185,6 +187,7 @@ gosh_status gosh_ctx_destroy(gosh_ctx* ctx) {
     }
     for (auto& kv : c->live) (void)hipFree(kv.first);
     for (auto& kv : c->cache) (void)hipFree(kv.second);
+    if (c->pinned) (void)hipHostFree(c->pinned);
     delete ctx;
     return GOSH_OK;
 }

@@ -747,11 +747,12 @@ unsigned long long* scratch_u64(Ctx* c, int slot) {
     return static_cast<unsigned long long*>(c->scratch) + slot;
 }
 
+// One device value read back through a pinned slot of the context (one wait).
 uint64_t read_u64(Ctx* c, const unsigned long long* p) {
-    unsigned long long h = 0;
-    GOSH_HIP(hipMemcpyAsync(&h, p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long* h = reinterpret_cast<unsigned long long*>(c->pinned + 2);
+    GOSH_HIP(hipMemcpyAsync(h, p, sizeof(*h), hipMemcpyDeviceToHost, c->stream));
     GOSH_HIP(hipStreamSynchronize(c->stream));
-    return h;
+    return *h;
 }
 
 template <class K>
@@ -928,10 +929,10 @@ DevBuf<int32_t> expand_rows(Ctx* c, const Off* off, int64_t n, int64_t nnz) {
 }
 
 unsigned int read_flags(Ctx* c, unsigned int* bad) {
-    unsigned int h = 0;
-    GOSH_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    unsigned int* h = reinterpret_cast<unsigned int*>(c->pinned + 3);
+    GOSH_HIP(hipMemcpyAsync(h, bad, 4, hipMemcpyDeviceToHost, c->stream));
     GOSH_HIP(hipStreamSynchronize(c->stream));
-    return h;
+    return *h;
 }
 
 // Structure checks of a caller's CSR; returns the row of every entry.
@@ -993,12 +994,13 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     // scan each segment with a whole wave
     DevBuf<uint8_t> state(c, n);
     fill(c, state.p, n, 0);
-    // two rounds per host check (a round over decided vertices changes
+    // three rounds per host check (a round over decided vertices changes
     // nothing, and the R-MAT levels take 2-4): the count read back is the
-    // second round's
-    for (int64_t round = 0;; round += 2) {
-        GOSH_REQUIRE(round <= n + 2, GOSH_E_DEVICE, "coarsening rounds did not converge");
-        for (int r = 0; r < 2; ++r) {
+    // last round's
+    constexpr int kRoundsPerCheck = 3;
+    for (int64_t round = 0;; round += kRoundsPerCheck) {
+        GOSH_REQUIRE(round <= n + kRoundsPerCheck, GOSH_E_DEVICE, "coarsening rounds did not converge");
+        for (int r = 0; r < kRoundsPerCheck; ++r) {
             GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
             if (dense)
                 hipLaunchKernelGGL(k_round_wave, grid_reduce(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
@@ -1111,6 +1113,12 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
     rank.reset();
     perm.reset();
 
+    // the assignment flag is copied now and read after the coarse build,
+    // which waits for the stream when it reads its entry count back
+    unsigned int* bad_h = reinterpret_cast<unsigned int*>(c->pinned + 4);
+    *bad_h = 0xFFFFFFFFu;
+    GOSH_HIP(hipMemcpyAsync(bad_h, bad, 4, hipMemcpyDeviceToHost, c->stream));
+
     // coarse graph: distinct pairs (map v, map u), map v != map u, rows
     // ascending; by cluster segments, or by one sort of all pair keys
     void* noff = nullptr;
@@ -1124,9 +1132,8 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
         else
             nnz_next = build_coarse<uint64_t>(c, src, idx, nnz, L.map, n_next, L.off64, &noff, &nidx);
     }
-    // the assignment flag was written before the syncs inside build_coarse
-    GOSH_REQUIRE(read_flags(c, bad) == 0, GOSH_E_BAD_GRAPH,
-                 "coarsening left a vertex without a cluster (graph not symmetric?)");
+    GOSH_REQUIRE(*bad_h != 0xFFFFFFFFu, GOSH_E_DEVICE, "coarse build returned before waiting for the stream");
+    GOSH_REQUIRE(*bad_h == 0, GOSH_E_BAD_GRAPH, "coarsening left a vertex without a cluster (graph not symmetric?)");
     next.n = n_next;
     next.nnz = nnz_next;
     next.off64 = L.off64;

@@ -61,6 +61,10 @@ struct Ctx {
     std::map<void*, size_t> live;
     // small device scratch for counters and flags
     void* scratch = nullptr;   // 4 KiB
+    // pinned host slots for single values read back from the device (a copy
+    // into pageable memory would block the host on its own)
+    int64_t* pinned = nullptr; // kPinnedSlots slots
+    static constexpr int kPinnedSlots = 64;
     // batched-training autotune cache: key -> (mode, blocks per CU, chunk iterations)
     std::map<std::string, std::array<int, 3>> tune;
     bool tune_loaded = false;

@@ -150,17 +150,17 @@ void scan_impl(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int
         if (total_host) *total_host = 0;
         return;
     }
-    // The last input is fetched before the scan because `out` may alias `in`.
-    T last_in{};
+    // The last input is fetched before the scan because `out` may alias `in`;
+    // both values land in the context's pinned slots, so the host waits once.
+    T* last_in = reinterpret_cast<T*>(c->pinned);
+    int64_t* last_out = c->pinned + 1;
     if (total_host && !inclusive)
-        GOSH_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(T), hipMemcpyDeviceToHost, c->stream));
+        GOSH_HIP(hipMemcpyAsync(last_in, in + n - 1, sizeof(T), hipMemcpyDeviceToHost, c->stream));
     scan_launch<T, OP>(c, in, out, n, inclusive);
     if (total_host) {
-        int64_t last_out = 0;
-        GOSH_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost,
-                                c->stream));
+        GOSH_HIP(hipMemcpyAsync(last_out, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
         GOSH_HIP(hipStreamSynchronize(c->stream));
-        *total_host = inclusive ? last_out : apply<OP>(last_out, static_cast<int64_t>(last_in));
+        *total_host = inclusive ? *last_out : apply<OP>(*last_out, static_cast<int64_t>(*last_in));
     }
 }
 
