@@ -190,12 +190,15 @@ struct RowIO<true> {
                 // per half: the exact rounded difference in one add, or,
                 // when out - cur is not a BF16 value, two exact adds through
                 // zero (-cur, then +out)
+                // the FP32 difference of two BF16 values is exact unless
+                // their exponents lie far apart; it is a BF16 value when its
+                // low half is zero, and then adding it back gives out again
                 const float c0 = bf16_lo(cur[i]), c1 = bf16_hi(cur[i]);
                 const float o0 = bf16_lo(want), o1 = bf16_hi(want);
-                const uint32_t h0 = bf16_rne_bits(o0 - c0) & 0xFFFFu;
-                const uint32_t h1 = bf16_rne_bits(o1 - c1) & 0xFFFFu;
-                const bool x0 = c0 + bf16_lo(h0) == o0;
-                const bool x1 = c1 + bf16_lo(h1) == o1;
+                const float d0 = o0 - c0, d1 = o1 - c1;
+                const uint32_t h0 = __float_as_uint(d0) >> 16, h1 = __float_as_uint(d1) >> 16;
+                const bool x0 = (__float_as_uint(d0) & 0xFFFFu) == 0u && c0 + d0 == o0;
+                const bool x1 = (__float_as_uint(d1) & 0xFFFFu) == 0u && c1 + d1 == o1;
                 const uint32_t a = (x0 ? h0 : (cur[i] & 0xFFFFu) ^ 0x8000u) |
                                    ((x1 ? h1 : (cur[i] >> 16) ^ 0x8000u) << 16);
                 const uint32_t b2 = (x0 ? 0u : want & 0xFFFFu) | (x1 ? 0u : want & 0xFFFF0000u);
