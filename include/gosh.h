@@ -280,11 +280,13 @@ gosh_status gosh_epoch_schedule(int32_t e, double p, int32_t D, int32_t* e_out);
  * M[u] += score M[src] with the updated source row.
  * `emb` is a caller-owned device array [n_level, d] of `dt`, updated in
  * place.  Sources of an epoch run concurrently; every row change is applied
- * atomically (FP32: atomic adds per element; BF16, per 2-element word: the
- * packed atomic add of the difference to the rounded value when that
- * difference is a BF16 value, else a compare-and-swap of the rounded pair),
- * so concurrent updates of a shared row are all kept and an uncontended
- * word holds exactly its rounded value.  BF16 rows are widened to FP32 for
+ * atomically by default (FP32: atomic adds per element; BF16, per 2-element
+ * word: the packed atomic add of the difference to the rounded value when
+ * that difference is a BF16 value, else two exact packed adds through zero,
+ * -cur then +rounded), so concurrent updates of a shared row are all kept
+ * and an uncontended word holds exactly its rounded value
+ * (gosh_set_plain_negatives and gosh_set_plain_light_rows store some rows
+ * plainly instead).  BF16 rows are widened to FP32 for
  * the arithmetic and every written row is stochastically rounded back
  * (sample rows once per update, the source row once per visit).  d in {8,16,32,64,128,256}, 0 <= k <= 15,
  * lr finite and >= 0.  `tag` (24 bits) separates independent random
