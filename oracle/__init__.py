@@ -1,9 +1,9 @@
 """GOSH CPU oracle -- test infrastructure only.
 
 A plain FP64 reference of the method of "Boosting Graph Embedding on a Single
-GPU" (arXiv 2110.10049), used by the tests, the smoke check and the
-benchmark's CPU-baseline leg to judge the HIP path.  The product path never
-imports it.  The arithmetic is in ``gosh_oracle.c`` (loaded with ctypes);
+GPU" (arXiv 2110.10049), used by the tests and the smoke check to check the
+HIP path, and timed by the benchmark's CPU-baseline leg.  The product path
+never imports it.  The arithmetic is in ``gosh_oracle.c`` (loaded with ctypes);
 this module adds numpy marshalling and the parts that are plain definitions:
 
   * coarsening levels with the stop rule of Algorithm 4
