@@ -116,6 +116,9 @@ def parse():
     ap.add_argument("--plain-light-min", type=int, default=262144,
                     help="plain stores for rows of at most average degree on levels of at least this many vertices "
                          "(0: off)")
+    ap.add_argument("--grouped", default="0,0,64",
+                    help="MIN,MAX,FACTOR: group the visits of hot positives (hubs of degree >= FACTOR x average) on "
+                         "levels with MIN <= n <= MAX (MAX 0: off)")
     ap.add_argument("--no-auc", action="store_true")
     ap.add_argument("--no-loss", action="store_true", help="skip the untimed running-loss passes")
     ap.add_argument("--lds-levels", type=int, default=0,
@@ -740,6 +743,8 @@ def main_workload(a):
     ctx.set_epoch_overlap(a.overlap, a.overlap_min)
     ctx.set_plain_negatives(a.plain_neg_min)
     ctx.set_plain_light_rows(a.plain_light_min)
+    _g = a.grouped.split(",")
+    ctx.set_grouped_positives(int(_g[0]), int(_g[1]), float(_g[2]))
     ctx.set_coarsen_mode(G.GOSH_COARSEN_LOCK_SKIP if a.coarsen == "lock-skip" else G.GOSH_COARSEN_EXACT)
     ctx.set_lds_levels(a.lds_levels)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
@@ -855,7 +860,8 @@ def main_workload(a):
                    "levels": bf["sizes"], "schedule": bf["schedule"], "seeds": seeds, "epoch_unit": "passes",
                    "epochs_per_launch": {"large_levels": a.overlap, "min_vertices": a.overlap_min},
                    "plain_negative_stores_min_vertices": a.plain_neg_min,
-                   "plain_light_rows_min_vertices": a.plain_light_min, "coarsening": a.coarsen,
+                   "plain_light_rows_min_vertices": a.plain_light_min,
+                   "grouped_positives": a.grouped, "coarsening": a.coarsen,
                    "updates_per_step": bf["updates_per_step"]},
         "roofline": roof(bf, 2, measured_traffic() if a.workload == "rmat20" and d == 128 else None),
         "train_ms_per_step": round(bf["train_ms"], 3),

@@ -196,6 +196,30 @@ gosh_status gosh_set_plain_negatives(gosh_ctx* ctx, int64_t min_vertices);
  * one launch per epoch.  0 (the default) turns it off.  min_vertices >= 0. */
 gosh_status gosh_set_plain_light_rows(gosh_ctx* ctx, int64_t min_vertices);
 
+/* Grouped visits of hot positives (a schedule of Algorithm 3's concurrent
+ * sources; Section 3.1): on levels with min_vertices <= n <= max_vertices,
+ * each epoch of gosh_train first draws every source's samples (the same
+ * draws) and files the visits whose positive is a hub of degree at least
+ * hot_factor times the level's average (the first 4,096 such ids) into one
+ * bucket per hub; one launch then runs the other visits and, per chunk of
+ * the bucketed visits of one hub (as many as a workgroup has lane groups),
+ * a workgroup that reads the hub row once, runs the chunk's visits against
+ * that copy with their changes to it summed in FP32, and commits the sum
+ * once (BF16: stochastically rounded once per chunk, exact commit).  No
+ * change is lost; a chunk's visits read the hub row as it was when the chunk
+ * started.  The draws of up to 16 epochs are made in one launch, into
+ * device memory of 4 (n (1+k) + the hubs' degree sum) bytes per epoch of the
+ * batch (batches kept within 256 MiB, at least one epoch), allocated per
+ * call.  Not used in deterministic mode, with overlapping epochs or on
+ * levels where light rows are stored plainly.  The result is one of the
+ * interleavings Algorithm 3's concurrent sources allow, but not the one the
+ * per-epoch launch takes: on the scale-20 R-MAT workload (level 1 grouped,
+ * hot_factor 64) the level after it ends with a last-epoch loss 1.5-2% above
+ * the ungrouped run's.  max_vertices = 0 (the default) turns it off;
+ * hot_factor defaults to 64.  min_vertices, max_vertices >= 0,
+ * hot_factor >= 1. */
+gosh_status gosh_set_grouped_positives(gosh_ctx* ctx, int64_t min_vertices, int64_t max_vertices, double hot_factor);
+
 /* Running loss of training (the objective of Section 2, the logistic loss of
  * the classifier sigma(M[v].M[u]) on the positive and negative samples).
  * When loss_dev is not NULL, every later gosh_train call adds to

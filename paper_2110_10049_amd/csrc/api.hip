@@ -273,6 +273,15 @@ gosh_status gosh_set_plain_light_rows(gosh_ctx* ctx, int64_t min_vertices) {
     return GOSH_OK;
 }
 
+gosh_status gosh_set_grouped_positives(gosh_ctx* ctx, int64_t min_vertices, int64_t max_vertices, double hot_factor) {
+    if (!ctx || min_vertices < 0 || max_vertices < 0 || !(hot_factor >= 1.0) || !std::isfinite(hot_factor))
+        return GOSH_E_INVALID_ARG;
+    ctx->c.group_min = min_vertices;
+    ctx->c.group_max = max_vertices;
+    ctx->c.group_factor = hot_factor;
+    return GOSH_OK;
+}
+
 gosh_status gosh_set_resident_epochs(gosh_ctx* ctx, int64_t max_vertices) {
     if (!ctx || max_vertices < 0) return GOSH_E_INVALID_ARG;
     ctx->c.resident_max = max_vertices;

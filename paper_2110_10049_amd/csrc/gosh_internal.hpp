@@ -46,6 +46,10 @@ struct Ctx {
     int64_t overlap_min = 0;   // levels with at least this many vertices overlap
     int64_t plain_neg_min = 0; // levels with at least this many vertices store negatives plainly (0: never)
     int64_t plain_light_min = 0; // levels with at least this many vertices store light rows plainly (0: never)
+    // levels with group_min <= n <= group_max train with the visits of hot
+    // positives grouped (hubs of degree >= group_factor x the average)
+    int64_t group_min = 0, group_max = 0;
+    double group_factor = 64.0;
     int64_t resident_max = 0;  // levels with at most this many vertices run all epochs in one launch (0: never)
     int64_t lds_max = 0;       // levels with at most this many vertices (and rows fitting in LDS) train in one workgroup
     int32_t* record = nullptr; // test hook: samples drawn inside gosh_train (device, caller-owned)

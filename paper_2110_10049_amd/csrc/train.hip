@@ -345,6 +345,9 @@ const uint32_t* hub_bits(Ctx* c, const Level& L, int64_t light_below) {
     return L.hub_bits;
 }
 
+bool train_level_grouped(Ctx* c, const Level& L, train_detail::TrainParams P, gosh_dtype dt, int d, int epochs,
+                         float lr);
+
 void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt, int d, int epochs,
                  float lr, int k, uint32_t tag, uint64_t* updates_dev) {
     check_train_args(dt, d, k, lr);
@@ -390,7 +393,12 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
                  "loss record buffer holds fewer entries than the call's epochs");
     const int64_t lds_bytes = lds_level_bytes(L.n, d, dt == GOSH_BF16 ? 2 : 4, k);
     const bool plain = P.plain_neg != 0 || P.light_below != 0;
-    if (!c->deterministic && span == 1 && !plain && L.n <= c->lds_max && lds_bytes <= kLdsMaxBytes) {
+    const bool grouped = !c->deterministic && span == 1 && P.light_below == 0 && c->group_max > 0 &&
+                         L.n >= c->group_min && L.n <= c->group_max && L.n < (int64_t(1) << 31) &&
+                         train_level_grouped(c, L, P, dt, d, epochs, lr);
+    if (grouped) {
+        // epochs ran with the visits of hot positives grouped (grouped.hip)
+    } else if (!c->deterministic && span == 1 && !plain && L.n <= c->lds_max && lds_bytes <= kLdsMaxBytes) {
         // the level's rows and one epoch's samples in one workgroup's LDS
         const ResidentKernel R = dt == GOSH_BF16 ? resident_d<true>(d, k, L.off64, true)
                                                  : resident_d<false>(d, k, L.off64, true);

@@ -48,7 +48,7 @@ struct TrainParams {
     double* loss;             // optional: running loss per epoch of the launch (index = epoch - first)
 };
 
-enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3, kLds = 4 };
+enum Mode { kEpoch = 0, kExplicit = 1, kSequential = 2, kPersistent = 3, kLds = 4, kTable = 5 };
 
 // Lane layout of a d-wide row.  A group of L lanes serves one row; lane gl
 // owns the 32-bit words gl + L*i, i < WPL (FP32: one element per word, BF16:
@@ -315,13 +315,18 @@ __device__ __forceinline__ float softplusf_(float z) {
 // source).  Returns, when want_loss, the visit's running loss: the
 // Section 2 objective of each executed update at the dot it reads (the same
 // value on every lane of the group); 0 otherwise.
-template <bool BF16, int D, int KMAX, bool COH, class IO = RowIO<BF16>>
+// HUB: the positive (u[0]) is a hub row held by the workgroup: its words
+// are read from hub_words (LDS, the row's layout) and its change is added to
+// hub_delta (LDS, FP32 per element) instead of being committed; the caller
+// commits the summed change once.
+template <bool BF16, int D, int KMAX, bool COH, class IO = RowIO<BF16>, bool HUB = false>
 __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, int64_t src,
                                               typename RowIO<BF16>::Elem* Mo, int64_t self,
                                               const int32_t (&u)[KMAX + 1], int k, float lr, uint32_t sid,
                                               uint32_t epoch, uint32_t w2, uint32_t sr_kind, uint32_t blk_hi,
                                               uint32_t key0, uint32_t key1, unsigned long long* updates, int gl,
-                                              uint32_t plain = 0u, bool want_loss = false) {
+                                              uint32_t plain = 0u, bool want_loss = false,
+                                              const uint32_t* hub_words = nullptr, float* hub_delta = nullptr) {
     using Ly = Lanes<BF16, D>;
     constexpr int L = Ly::kL;
     constexpr int E = Ly::kEPL;
@@ -336,7 +341,10 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
         IO::template load<D, COH>(Ms, src, gl, sw);
 #pragma unroll
         for (int t = 0; t <= KMAX; ++t) {
-            if (t <= k && u[t] >= 0 && u[t] != self) {
+            if (HUB && t == 0) {
+#pragma unroll
+                for (int i = 0; i < W; ++i) mw[0][i] = hub_words[gl + L * i];
+            } else if (t <= k && u[t] >= 0 && u[t] != self) {
                 IO::template load<D, COH>(Mo, u[t], gl, mw[t]);
             } else {
 #pragma unroll
@@ -388,6 +396,16 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
                 v[2 * i] = fmaf(g, s[2 * i], bf16_lo(mw[t][i]));
                 v[2 * i + 1] = fmaf(g, s[2 * i + 1], bf16_hi(mw[t][i]));
             }
+            if (HUB && t == 0) {
+                // the hub's change, summed over the workgroup's visits
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    atomicAdd(&hub_delta[2 * (gl + L * i)], v[2 * i] - bf16_lo(mw[0][i]));
+                    atomicAdd(&hub_delta[2 * (gl + L * i) + 1], v[2 * i + 1] - bf16_hi(mw[0][i]));
+                }
+                ++done;
+                continue;
+            }
             uint32_t out[W];
             if ((plain >> t) & 1u) IO::template commit<D, true>(Mo, ut, gl, mw[t], v, bits, out);
             else IO::template commit<D>(Mo, ut, gl, mw[t], v, bits, out);
@@ -407,7 +425,10 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
         IO::template load<D, COH>(Ms, src, gl, s);
 #pragma unroll
         for (int t = 0; t <= KMAX; ++t) {
-            if (t <= k && u[t] >= 0 && u[t] != self) {
+            if (HUB && t == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) m[0][e] = __uint_as_float(hub_words[gl + L * e]);
+            } else if (t <= k && u[t] >= 0 && u[t] != self) {
                 IO::template load<D, COH>(Mo, u[t], gl, m[t]);
             } else {
 #pragma unroll
@@ -451,8 +472,14 @@ __device__ __forceinline__ float update_chain(typename RowIO<BF16>::Elem* Ms, in
                 dx[e] = g * s[e];
                 m[t][e] += dx[e];
             }
-            if ((plain >> t) & 1u) IO::template store<D>(Mo, ut, gl, m[t]);
-            else IO::template add<D>(Mo, ut, gl, dx);
+            if (HUB && t == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) atomicAdd(&hub_delta[gl + L * e], dx[e]);
+            } else if ((plain >> t) & 1u) {
+                IO::template store<D>(Mo, ut, gl, m[t]);
+            } else {
+                IO::template add<D>(Mo, ut, gl, dx);
+            }
             ++done;
         }
         if (done) {
@@ -488,12 +515,14 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
 #pragma unroll
     for (int t = 0; t <= KMAX; ++t) u[t] = -1;
 
-    if constexpr (MODE == kLds) {
-        // the epoch's samples were drawn into the table P.samples beforehand
+    if constexpr (MODE == kLds || MODE == kTable) {
+        // the epoch's samples were drawn into the table P.samples beforehand;
+        // in kTable a first entry below -1 marks a visit another pass takes
         if (active) {
 #pragma unroll
             for (int t = 0; t <= KMAX; ++t)
                 if (t <= k) u[t] = P.samples[slot * (1 + k) + t];
+            if (MODE == kTable && u[0] < -1) active = false;
         }
     } else if constexpr (MODE == kExplicit) {
         if (active) {
@@ -558,7 +587,7 @@ __device__ __forceinline__ float visit(const TrainParams& P, int64_t slot, bool 
         }
     }
     if (!active) return 0.0f;
-    if ((MODE == kEpoch || MODE == kExplicit || MODE == kSequential) && P.plain_neg != 0)
+    if ((MODE == kEpoch || MODE == kExplicit || MODE == kSequential || MODE == kTable) && P.plain_neg != 0)
         plain |= ((2u << KMAX) - 1u) & ~1u;   // every negative slot
     return update_chain<BF16, D, KMAX, MODE == kPersistent, IO>(
         M, src, M, src, u, k, P.lr, static_cast<uint32_t>(src), P.epoch, P.w2, 1u, 0u, P.key0, P.key1, P.updates,

@@ -85,6 +85,7 @@ _SIGNATURES = [
     ("gosh_set_epoch_overlap", C.c_int, [_P, C.c_int32, C.c_int64]),
     ("gosh_set_plain_negatives", C.c_int, [_P, C.c_int64]),
     ("gosh_set_plain_light_rows", C.c_int, [_P, C.c_int64]),
+    ("gosh_set_grouped_positives", C.c_int, [_P, C.c_int64, C.c_int64, C.c_double]),
     ("gosh_set_loss_record", C.c_int, [_P, _P, C.c_int64]),
     ("gosh_set_resident_epochs", C.c_int, [_P, C.c_int64]),
     ("gosh_set_lds_levels", C.c_int, [_P, C.c_int64]),
@@ -224,6 +225,10 @@ class Context:
     def set_plain_negatives(self, min_vertices: int):
         """Plain stores for negative rows on levels of at least min_vertices vertices (0 = off)."""
         self.check(self._L.gosh_set_plain_negatives(self.h, min_vertices))
+
+    def set_grouped_positives(self, min_vertices: int, max_vertices: int, hot_factor: float = 64.0):
+        """Group the visits of hot positives on levels with min <= n <= max (max 0 = off)."""
+        self.check(self._L.gosh_set_grouped_positives(self.h, min_vertices, max_vertices, hot_factor))
 
     def set_plain_light_rows(self, min_vertices: int):
         """Plain stores for rows of at most average degree on levels of at least min_vertices vertices (0 = off)."""

@@ -5,8 +5,9 @@ epoch concurrently, the oracle in order, so only the score is compared).
 The scale-20 workload (d = 128, k = 3, 600 epochs) is compared with the
 oracle's stored result (tests/golden/e2e_auc_rmat20.json, written by
 tests/golden/make_e2e_auc.py from oracle/ alone), in FP32 and BF16, with atomic
-row updates everywhere and with the benchmark's plain negative stores on
-levels of at least 262,144 vertices."""
+row updates everywhere, with the benchmark's plain negative stores and plain
+light-row stores on levels of at least 262,144 vertices, and with the visits
+of hot positives grouped on level 1."""
 import json
 import os
 
@@ -192,15 +193,18 @@ def test_plain_negative_stores_zero_lr_is_identity(gctx, dtype):
         gctx.set_plain_negatives(-1)
 
 
-@pytest.mark.parametrize("plain_min,light_min", [(0, 0), (262144, 0), (262144, 262144)])
+@pytest.mark.parametrize("plain_min,light_min,grouped", [(0, 0, False), (262144, 0, False), (262144, 262144, False),
+                                                        (0, 0, True)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-def test_config2_auc_matches_oracle(gctx, dtype, plain_min, light_min):
+def test_config2_auc_matches_oracle(gctx, dtype, plain_min, light_min, grouped):
     """Scale-20 R-MAT, d = 128, k = 3, 600 epochs (the benchmark's workload):
     the same levels, schedule and update count as the oracle, AUC within
     0.01 of the oracle's, and the last epoch's running loss of every level
     within 5% of the sequential oracle's; with atomic commits everywhere,
-    with plain negative stores on levels of at least 262,144 vertices, and
-    with those plus plain stores of light rows on levels of at least 65,536."""
+    with plain negative stores on levels of at least 262,144 vertices, with
+    those plus plain stores of light rows on that level, and with atomic
+    commits and the visits of hot positives grouped on the one level of
+    65,536 to 262,143 vertices (hubs of at least 64 x the average degree)."""
     from paper_2110_10049_amd import gosh as G
     from paper_2110_10049_amd.driver import EmbedConfig, embed
     gold = json.load(open(GOLD_C2))
@@ -209,12 +213,13 @@ def test_config2_auc_matches_oracle(gctx, dtype, plain_min, light_min):
     sp = train_split(c["scale"], c["edge_factor"], c["seeds"]["graph"], c["seeds"]["split"])
     if "c2" not in _PAIRS:
         _PAIRS["c2"] = make_eval_pairs(sp, c["seeds"]["eval"], c["eval"]["max_train"], c["eval"]["max_test"])
-    print(f"[e2e config2] dtype={dtype} plain_min={plain_min} light_min={light_min}", flush=True)
+    print(f"[e2e config2] dtype={dtype} plain_min={plain_min} light_min={light_min} grouped={grouped}", flush=True)
     g = G.CSR.from_numpy(sp.offsets, sp.indices)
     cfg = EmbedConfig(d=c["d"], epochs=c["epochs"], p=c["p"], lr=c["lr"], k=c["k"], dtype=dtype,
                       threshold=c["threshold"], epoch_unit=c["epoch_unit"])
     gctx.set_plain_negatives(plain_min)
     gctx.set_plain_light_rows(light_min)
+    gctx.set_grouped_positives(65536, 262143 if grouped else 0, 64.0)
     try:
         res = embed(gctx, g, cfg,
                     lambda n, d: torch.from_numpy(init_rows(n, d, c["seeds"]["init"])).cuda().to(dtype),
@@ -223,6 +228,7 @@ def test_config2_auc_matches_oracle(gctx, dtype, plain_min, light_min):
     finally:
         gctx.set_plain_negatives(0)
         gctx.set_plain_light_rows(0)
+        gctx.set_grouped_positives(0, 0)
     assert res.sizes == ref["sizes"]
     assert list(res.schedule) == ref["schedule"]
     assert int(res.updates.item()) == ref["updates"]
