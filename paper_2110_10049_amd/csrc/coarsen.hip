@@ -112,30 +112,83 @@ __global__ void k_expand_rows(const Off* off, int64_t n, int32_t* src) {
 }
 
 // ---------------------------------------------------------------- eligible edges to earlier vertices
-__global__ void k_flag_lower(const int32_t* src, const int32_t* idx, int64_t nnz, const uint8_t* light,
-                             const int32_t* rank, int32_t* flag) {
-    GRID_STRIDE(p, nnz) {
-        const int32_t v = src[p], u = idx[p];
-        flag[p] = ((light[v] | light[u]) && rank[u] < rank[v]) ? 1 : 0;
+// Entry p = (v, u) is kept when one end is light and u comes earlier in pi.
+// The kept entries are compacted in CSR order, so vertex v's eligible
+// earlier neighbours form the segment [lstart[v], lstart[v+1]) of `lower`.
+// The keep decisions (two random lookups per entry) are taken once, into a
+// bit per entry (word w holds entries 64 w .. 64 w + 63), with each word's
+// count of kept entries before it in its tile of kLowerTile entries and
+// each tile's count; an exclusive sum over the tiles then places every
+// entry and every row start without a second pass over the lookups.
+constexpr int kLowerItems = 16;
+constexpr int64_t kLowerTile = int64_t(kThreads) * kLowerItems;
+constexpr int kLowerWords = static_cast<int>(kLowerTile / 64);   // 64 words per tile
+
+__global__ __launch_bounds__(kThreads) void k_lower_bits(const int32_t* src, const int32_t* idx, int64_t nnz,
+                                                         const uint8_t* light, const int32_t* rank,
+                                                         unsigned long long* bits, uint16_t* wpre,
+                                                         int64_t* tile_cnt) {
+    __shared__ int wc[kLowerWords];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kLowerTile;
+#pragma unroll 4
+    for (int r = 0; r < kLowerItems; ++r) {
+        const int64_t p = base + r * kThreads + threadIdx.x;
+        bool keep = false;
+        if (p < nnz) {
+            const int32_t v = src[p], u = idx[p];
+            keep = (light[v] | light[u]) && rank[u] < rank[v];
+        }
+        const unsigned long long m = __ballot(keep);
+        const int word = r * (kThreads / 64) + w;   // entries base + 64 word .. + 63
+        if (lane == 0) {
+            wc[word] = __popcll(m);
+            if (base + 64 * word < nnz) bits[(base >> 6) + word] = m;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {   // exclusive prefix of the 64 word counts, one wave
+        const int c = wc[lane];
+        int inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (base + 64 * lane < nnz) wpre[(base >> 6) + lane] = static_cast<uint16_t>(inc - c);
+        if (lane == 63) tile_cnt[blockIdx.x] = inc;
     }
 }
 
-// The kept entries stay in CSR order, so vertex v's eligible earlier
-// neighbours form the segment [lstart[v], lstart[v+1]) of `lower`.
-__global__ void k_write_lower(const int32_t* idx, int64_t nnz, const int32_t* flag, const int64_t* pos,
-                              int32_t* lower) {
+// Kept entry p goes to tile_base[p / kLowerTile] + wpre[p / 64] + (kept
+// entries before p in its word).
+__global__ void k_lower_write(const int32_t* idx, int64_t nnz, const unsigned long long* bits,
+                              const uint16_t* wpre, const int64_t* tile_base, int32_t* lower) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     GRID_STRIDE(p, nnz) {
-        if (flag[p]) lower[pos[p]] = idx[p];
+        const int64_t word = p >> 6;
+        const unsigned long long m = bits[word];
+        if ((m >> lane) & 1ull)
+            lower[tile_base[p / kLowerTile] + wpre[word] + __popcll(m & lt)] = idx[p];
     }
 }
 
+// lstart[v] = kept entries before off[v] (v = 0..n); tile_base has tiles + 1
+// entries, the last the total.
 template <class Off>
-__global__ void k_lower_starts(const Off* off, int64_t n, int64_t nnz, const int32_t* flag, const int64_t* pos,
-                               int64_t* lstart) {
-    const int64_t m = nnz > 0 ? pos[nnz - 1] + flag[nnz - 1] : 0;
+__global__ void k_lower_starts(const Off* off, int64_t n, int64_t nnz, const unsigned long long* bits,
+                               const uint16_t* wpre, const int64_t* tile_base, int64_t tiles, int64_t* lstart) {
     GRID_STRIDE(v, n + 1) {
-        const int64_t o = off[v];
-        lstart[v] = o < nnz ? pos[o] : m;
+        const int64_t e = off[v];
+        if (e >= nnz) {
+            lstart[v] = tile_base[tiles];
+        } else {
+            const int64_t word = e >> 6;
+            const int b = static_cast<int>(e & 63);
+            const unsigned long long below = b == 0 ? 0ull : (bits[word] & (~0ull >> (64 - b)));
+            lstart[v] = tile_base[e / kLowerTile] + wpre[word] + __popcll(below);
+        }
     }
 }
 
@@ -972,21 +1025,25 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     const int64_t n = L.n, nnz = L.nnz;
     DevBuf<int32_t> lower(c, std::max<int64_t>(nnz, 1));
     DevBuf<int64_t> lstart(c, n + 1);
-    {
-        DevBuf<int32_t> flag(c, std::max<int64_t>(nnz, 1));
-        DevBuf<int64_t> pos(c, std::max<int64_t>(nnz, 1));
-        if (nnz > 0) {
-            hipLaunchKernelGGL(k_flag_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, src, idx, nnz,
-                               light_p, rank_p, flag.p);
-            GOSH_HIP(hipGetLastError());
-            scan_i32_to_i64(c, flag.p, pos.p, nnz, nullptr);
-            hipLaunchKernelGGL(k_write_lower, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, flag.p,
-                               pos.p, lower.p);
-            GOSH_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL((k_lower_starts<Off>), grid_for(n + 1), dim3(kThreads), 0, c->stream, off, n, nnz,
-                           flag.p, pos.p, lstart.p);
+    if (nnz > 0) {
+        const int64_t tiles = ceil_div(nnz, kLowerTile);
+        const int64_t words = ceil_div(nnz, int64_t(64));
+        DevBuf<unsigned long long> bits(c, words);
+        DevBuf<uint16_t> wpre(c, words);
+        DevBuf<int64_t> tile(c, tiles + 1);
+        fill(c, tile.p + tiles, 1, 0);
+        hipLaunchKernelGGL(k_lower_bits, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, c->stream, src, idx,
+                           nnz, light_p, rank_p, bits.p, wpre.p, tile.p);
         GOSH_HIP(hipGetLastError());
+        scan_i64(c, tile.p, tile.p, tiles + 1, false, ScanOp::Sum, nullptr);
+        hipLaunchKernelGGL(k_lower_write, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, bits.p, wpre.p,
+                           tile.p, lower.p);
+        GOSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_lower_starts<Off>), grid_for(n + 1), dim3(kThreads), 0, c->stream, off, n, nnz, bits.p,
+                           wpre.p, tile.p, tiles, lstart.p);
+        GOSH_HIP(hipGetLastError());
+    } else {
+        fill(c, lstart.p, n + 1, 0);
     }
 
     // hub selection rounds; each round decides at least the earliest

@@ -166,14 +166,16 @@ void scan_impl(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int
 
 // ---------------------------------------------------------------- radix sort
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kWaves = kSortThreads / 64;
 
-template <class K>
+// ITEMS keys per thread: a tile of ITEMS * 256 keys per workgroup (16 for
+// large inputs; 4 when 16 would leave most compute units without a tile)
+template <class K, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, int64_t n, int shift,
                                                              int64_t* hist, int64_t nb) {
+    constexpr int kSortItems = ITEMS;
+    constexpr int kSortTile = kSortThreads * ITEMS;
     __shared__ int cnt[kRadix];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -193,12 +195,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, int6
 // earlier waves of its round, earlier lanes of its wave found with 8 ballots)
 // and placed at its tile-local position in LDS, so that the final copy to
 // the output writes each digit's run of the tile with consecutive lanes.
-template <class K, bool VALS>
+template <class K, bool VALS, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K* keys_out,
                                                                 const uint32_t* vals,
                                                                 uint32_t* vals_out, int64_t n,
                                                                 int shift, const int64_t* offs,
                                                                 int64_t nb) {
+    constexpr int kSortItems = ITEMS;
+    constexpr int kSortTile = kSortThreads * ITEMS;
     __shared__ int64_t base_off[kRadix];     // output position of the tile's first key of each digit
     __shared__ int local_start[kRadix];      // tile position of the first key of each digit
     __shared__ int placed[kRadix];           // keys of each digit placed by earlier rounds
@@ -291,22 +295,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K
 }
 
 
-template <class K, bool VALS>
+template <class K, bool VALS, int ITEMS>
 void radix_sort_impl(Ctx* c, K* keys, K* keys_tmp, uint32_t* vals, uint32_t* vals_tmp, int64_t n,
                      int bits) {
     if (n <= 1 || bits <= 0) return;
-    const int64_t nb = ceil_div(n, kSortTile);
+    const int64_t nb = ceil_div(n, static_cast<int64_t>(kSortThreads) * ITEMS);
     DevBuf<int64_t> hist(c, static_cast<size_t>(nb) * kRadix);
     K* src = keys;
     K* dst = keys_tmp;
     uint32_t* vsrc = vals;
     uint32_t* vdst = vals_tmp;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL((k_radix_hist<K>), dim3(nb), dim3(kSortThreads), 0, c->stream, src, n,
+        hipLaunchKernelGGL((k_radix_hist<K, ITEMS>), dim3(nb), dim3(kSortThreads), 0, c->stream, src, n,
                            shift, hist.p, nb);
         GOSH_HIP(hipGetLastError());
         scan_impl<int64_t, ScanOp::Sum>(c, hist.p, hist.p, nb * kRadix, false, nullptr);
-        hipLaunchKernelGGL((k_radix_scatter<K, VALS>), dim3(nb), dim3(kSortThreads), 0, c->stream,
+        hipLaunchKernelGGL((k_radix_scatter<K, VALS, ITEMS>), dim3(nb), dim3(kSortThreads), 0, c->stream,
                            src, dst, vsrc, vdst, n, shift, hist.p, nb);
         GOSH_HIP(hipGetLastError());
         std::swap(src, dst);
@@ -332,14 +336,24 @@ void scan_i32_to_i64(Ctx* c, const int32_t* in, int64_t* out, int64_t n, int64_t
     scan_impl<int32_t, ScanOp::Sum>(c, in, out, n, false, total_host);
 }
 
+// Inputs below kLargeSort keys sort in tiles of 1,024 keys (a tile of 4,096
+// would leave most of the 256 compute units idle on a coarse level).
+constexpr int64_t kLargeSort = int64_t(4) << 20;
+
 void radix_sort_u32(Ctx* c, uint32_t* keys, uint32_t* keys_tmp, uint32_t* vals,
                     uint32_t* vals_tmp, int64_t n, int bits) {
-    if (vals) radix_sort_impl<uint32_t, true>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
-    else radix_sort_impl<uint32_t, false>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+    if (n >= kLargeSort) {
+        if (vals) radix_sort_impl<uint32_t, true, 16>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
+        else radix_sort_impl<uint32_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+    } else {
+        if (vals) radix_sort_impl<uint32_t, true, 4>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
+        else radix_sort_impl<uint32_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+    }
 }
 
 void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits) {
-    radix_sort_impl<uint64_t, false>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+    if (n >= kLargeSort) radix_sort_impl<uint64_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+    else radix_sort_impl<uint64_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
 }
 
 }  // namespace gosh
