@@ -422,6 +422,8 @@ __global__ void k_offsets_lb(const K* ukeys, int64_t m, int64_t n_next, int bb, 
 constexpr int kSegSmall = 4096;     // entries of a segment deduplicated by one wave
 constexpr int kGiantChunk = 16384;  // entries of a long segment per workgroup
 constexpr int kSegWaves = 4;
+constexpr int kSegBatch = 8;        // entries per lane loaded before their bitmap updates
+constexpr int kSegDenseWords = 256; // bitmap words (ids < 8192: the hub clusters) read back densely
 constexpr int64_t kSegMaxWords = 8192;   // bitmap words per wave (next level of at most 262,144 vertices)
 constexpr uint32_t kSegSent = 0xFFFFFFFFu;
 
@@ -483,58 +485,83 @@ __device__ __forceinline__ void wave_lds_sync() {
 // all W words back 64 at a time, each lane placing its word's ids after a
 // wave prefix sum of the popcounts.  A shorter one (level 0: a few hundred
 // entries against thousands of words) also marks a summary with one bit per
-// bitmap word (S = ceil(W / 32) words after the bitmap), and lane l reads
-// back only the marked words of its summary words [l q, l q + q), so the
-// segment costs its entries, not the words of the bitmap.
+// bitmap word (S = ceil(W / 32) words after the bitmap).  Its first
+// kSegDenseWords words -- the ids of the level's hub clusters, which most
+// segments reach (71% of a level-0 segment's ids) -- are read back by all
+// lanes 64 at a time; past them lane l reads back only the marked words of
+// its summary words, so the segment costs its entries, not the words of the
+// bitmap, and no lane is left with most of them.
 __global__ __launch_bounds__(64 * kSegWaves) void k_dedup_small(const int64_t* segstart, int64_t n_next, int W,
                                                                 uint32_t* raw, int32_t* cnt) {
     extern __shared__ uint32_t seg_bitmaps[];
     const int lane = threadIdx.x & 63;
     const int S = (W + 31) >> 5;
-    const int q = (S + 63) >> 6;
     uint32_t* bm = seg_bitmaps + static_cast<int64_t>(threadIdx.x >> 6) * (W + S);
     uint32_t* sm = bm + W;
     for (int w = lane; w < W + S; w += 64) bm[w] = 0u;
     wave_lds_sync();
     const int64_t nw = static_cast<int64_t>(gridDim.x) * kSegWaves;
-    for (int64_t c = static_cast<int64_t>(blockIdx.x) * kSegWaves + (threadIdx.x >> 6); c < n_next; c += nw) {
-        const int64_t s0 = segstart[c];
-        const int64_t len = segstart[c + 1] - s0;
+    int64_t c = static_cast<int64_t>(blockIdx.x) * kSegWaves + (threadIdx.x >> 6);
+    // the bounds of the wave's next segment are loaded while it works on the
+    // current one, and a segment's entries kSegBatch per lane at a time: a
+    // level-0 segment (about 270 entries) then costs one dependent round trip
+    // to memory instead of six
+    int64_t nb0 = c < n_next ? segstart[c] : 0, nb1 = c < n_next ? segstart[c + 1] : 0;
+    for (; c < n_next; c += nw) {
+        const int64_t s0 = nb0;
+        const int64_t len = nb1 - s0;
+        if (c + nw < n_next) {
+            nb0 = segstart[c + nw];
+            nb1 = segstart[c + nw + 1];
+        }
         if (len > kSegSmall) continue;   // a hub cluster: chunked with the others
         const bool sparse = static_cast<int64_t>(W) > 2 * len;   // wave-uniform
-        const int w0 = 0, w1 = W - 1;
-        for (int64_t i = lane; i < len; i += 64) {
-            const uint32_t x = raw[s0 + i];
-            if (x != kSegSent) {
-                atomicOr(&bm[x >> 5], 1u << (x & 31u));
-                if (sparse) atomicOr(&sm[x >> 10], 1u << ((x >> 5) & 31u));
+        for (int64_t i0 = 0; i0 < len; i0 += 64 * kSegBatch) {
+            uint32_t x[kSegBatch];
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u) {
+                const int64_t i = i0 + u * 64 + lane;
+                x[u] = i < len ? raw[s0 + i] : kSegSent;
+            }
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u) {
+                if (x[u] != kSegSent) {
+                    atomicOr(&bm[x[u] >> 5], 1u << (x[u] & 31u));
+                    if (sparse) atomicOr(&sm[x[u] >> 10], 1u << ((x[u] >> 5) & 31u));
+                }
             }
         }
         wave_lds_sync();
         int total = 0;
-        if (!sparse) {
-            for (int base = w0; base <= w1; base += 64) {
-                const int w = base + lane;
-                uint32_t word = w <= w1 ? bm[w] : 0u;
-                const int pc = __popc(word);
-                int incl = pc;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += t;
-                }
-                int64_t pos = s0 + total + (incl - pc);
-                if (w <= w1) bm[w] = 0u;
-                while (word) {
-                    const int bit = __ffs(word) - 1;
-                    raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
-                    word &= word - 1u;
-                }
-                total += __shfl(incl, 63, 64);
+        // words [0, P) read back by all lanes, 64 at a time, in order
+        const int P = sparse ? min(W, kSegDenseWords) : W;
+        for (int base = 0; base < P; base += 64) {
+            const int w = base + lane;
+            uint32_t word = w < P ? bm[w] : 0u;
+            const int pc = __popc(word);
+            int incl = pc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
             }
-        } else {
+            int64_t pos = s0 + total + (incl - pc);
+            if (w < P) bm[w] = 0u;
+            while (word) {
+                const int bit = __ffs(word) - 1;
+                raw[pos++] = (static_cast<uint32_t>(w) << 5) | static_cast<uint32_t>(bit);
+                word &= word - 1u;
+            }
+            total += __shfl(incl, 63, 64);
+        }
+        if (sparse) {
+            // the rest through the summary: each lane takes qq summary words
+            // (32 bitmap words each) past the s_lo that cover [0, P)
+            const int s_lo = P == W ? S : (P >> 5);
+            for (int i = lane; i < s_lo; i += 64) sm[i] = 0u;
+            const int qq = (S - s_lo + 63) >> 6;
             int pc = 0;
-            for (int j = 0; j < q; ++j) {
-                const int sidx = lane * q + j;
+            for (int j = 0; j < qq; ++j) {
+                const int sidx = s_lo + lane * qq + j;
                 if (sidx < S) {
                     uint32_t sw = sm[sidx];
                     while (sw) {
@@ -549,10 +576,10 @@ __global__ __launch_bounds__(64 * kSegWaves) void k_dedup_small(const int64_t* s
                 const int t = __shfl_up(incl, o, 64);
                 if (lane >= o) incl += t;
             }
-            total = __shfl(incl, 63, 64);
-            int64_t pos = s0 + (incl - pc);
-            for (int j = 0; j < q; ++j) {
-                const int sidx = lane * q + j;
+            int64_t pos = s0 + total + (incl - pc);
+            total += __shfl(incl, 63, 64);
+            for (int j = 0; j < qq; ++j) {
+                const int sidx = s_lo + lane * qq + j;
                 if (sidx < S) {
                     uint32_t sw = sm[sidx];
                     while (sw) {

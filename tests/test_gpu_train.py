@@ -87,7 +87,7 @@ def test_update_batch_fp32(gctx, orc, d, k):
     assert np.array_equal(got[untouched], M0[untouched].astype(np.float64))
 
 
-@pytest.mark.parametrize("d", [8, 32, 64, 128, 256])
+@pytest.mark.parametrize("d", [8, 16, 32, 64, 128, 256])
 @pytest.mark.parametrize("k", [1, 3, 15])
 def test_update_batch_bf16(gctx, orc, d, k):
     from paper_2110_10049_amd import gosh as G
