@@ -163,7 +163,6 @@ struct GroupArgs {
     const int64_t* cstart;
     int32_t n_hot;
     int64_t hot_blocks;
-    uint32_t chunk_base;   // stream counter of the epoch's hub commits
 };
 
 // hot_blocks of the launch's workgroups take the bucket chunks, the others
@@ -259,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_train_grouped(TrainParams P, GroupAr
                     v[2 * i + 1] = bf16_hi(cur[i]) + hub_delta[2 * (gl + L * i) + 1];
                 }
                 const uint4 bits = philox10(
-                    make_uint4(A.chunk_base + static_cast<uint32_t>(t), P.epoch, P.w2,
+                    make_uint4(static_cast<uint32_t>(t), P.epoch, P.w2,
                                stream_word3(9u, 0u, static_cast<uint32_t>(gl % Ly::kBlocks))),
                     P.key0, P.key1);
                 uint32_t out[W];
@@ -400,7 +399,7 @@ bool train_level_grouped(Ctx* c, const Level& L, TrainParams P, gosh_dtype dt, i
         P.loss = c->loss ? c->loss + j : nullptr;
         P.samples = table.p + jb * tstride;
         const GroupArgs A{hub_of.p, bstart.p, cap.p, cnt.p + jb * cstride, list.p + jb * lstride,
-                          cstart.p + jb * (n_hot + 1), n_hot, kHotBlocks, 0u};
+                          cstart.p + jb * (n_hot + 1), n_hot, kHotBlocks};
         fn(P, A, n, c->stream);
         GOSH_HIP(hipGetLastError());
     }
