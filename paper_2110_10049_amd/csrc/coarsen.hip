@@ -124,10 +124,15 @@ constexpr int kLowerItems = 16;
 constexpr int64_t kLowerTile = int64_t(kThreads) * kLowerItems;
 constexpr int kLowerWords = static_cast<int>(kLowerTile / 64);   // 64 words per tile
 
+// rl[v] = rank of v in pi, with bit 31 set when v is light: the keep test
+// then takes one random lookup per entry instead of two
+__global__ void k_pack_rank_light(const int32_t* rank, const uint8_t* light, int64_t n, uint32_t* rl) {
+    GRID_STRIDE(v, n) rl[v] = static_cast<uint32_t>(rank[v]) | (light[v] ? 0x80000000u : 0u);
+}
+
 __global__ __launch_bounds__(kThreads) void k_lower_bits(const int32_t* src, const int32_t* idx, int64_t nnz,
-                                                         const uint8_t* light, const int32_t* rank,
-                                                         unsigned long long* bits, uint16_t* wpre,
-                                                         int64_t* tile_cnt) {
+                                                         const uint32_t* rl, unsigned long long* bits,
+                                                         uint16_t* wpre, int64_t* tile_cnt) {
     __shared__ int wc[kLowerWords];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kLowerTile;
@@ -136,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_lower_bits(const int32_t* src, con
         const int64_t p = base + r * kThreads + threadIdx.x;
         bool keep = false;
         if (p < nnz) {
-            const int32_t v = src[p], u = idx[p];
-            keep = (light[v] | light[u]) && rank[u] < rank[v];
+            const uint32_t kv = rl[src[p]], ku = rl[idx[p]];
+            keep = ((kv | ku) >> 31) != 0u && (ku & 0x7FFFFFFFu) < (kv & 0x7FFFFFFFu);
         }
         const unsigned long long m = __ballot(keep);
         const int word = r * (kThreads / 64) + w;   // entries base + 64 word .. + 63
@@ -1058,9 +1063,12 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
         DevBuf<unsigned long long> bits(c, words);
         DevBuf<uint16_t> wpre(c, words);
         DevBuf<int64_t> tile(c, tiles + 1);
+        DevBuf<uint32_t> rl(c, n);
         fill(c, tile.p + tiles, 1, 0);
+        hipLaunchKernelGGL(k_pack_rank_light, grid_for(n), dim3(kThreads), 0, c->stream, rank_p, light_p, n, rl.p);
+        GOSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_lower_bits, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, c->stream, src, idx,
-                           nnz, light_p, rank_p, bits.p, wpre.p, tile.p);
+                           nnz, rl.p, bits.p, wpre.p, tile.p);
         GOSH_HIP(hipGetLastError());
         scan_i64(c, tile.p, tile.p, tiles + 1, false, ScanOp::Sum, nullptr);
         hipLaunchKernelGGL(k_lower_write, grid_for(nnz), dim3(kThreads), 0, c->stream, idx, nnz, bits.p, wpre.p,
