@@ -198,58 +198,48 @@ __global__ void k_lower_starts(const Off* off, int64_t n, int64_t nnz, const uns
 }
 
 // ---------------------------------------------------------------- hub selection rounds
+constexpr int kSparseGroup = 8;   // lanes per vertex in the rounds and the assignment of sparse levels
 // In place: a decision only uses states that are final (IN, OUT), so reading
 // a neighbour before or after its own decision in the same round is safe.
-__global__ void k_round(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
-                        unsigned long long* undecided) {
-    unsigned long long cnt = 0;
-    GRID_STRIDE(v, n) {
-        if (state[v] != kUndecided) continue;
-        bool any_in = false, pending = false;
-        for (int64_t i = lstart[v], e = lstart[v + 1]; i < e; ++i) {
-            const uint8_t su = state[lower[i]];
-            if (su == kIn) {
-                any_in = true;
-                break;
-            }
-            pending |= (su == kUndecided);
-        }
-        if (any_in) state[v] = kOut;
-        else if (!pending) state[v] = kIn;
-        else ++cnt;
-    }
-    block_fold<0>(undecided, cnt);
-}
-
-// The same decision with one wave per vertex, for dense levels whose
-// segments run to hundreds of entries: lanes split the segment, ballots
-// combine (reading every entry instead of stopping at the first IN gives the
-// same decision).
-__global__ void k_round_wave(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
-                             unsigned long long* undecided) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wpb = blockDim.x >> 6;
-    unsigned long long cnt = 0;
-    for (int64_t v = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); v < n;
-         v += static_cast<int64_t>(gridDim.x) * wpb) {
+// The round's decision with GL lanes per vertex (GL = 64 on dense levels
+// whose segments run to hundreds of entries, 8 on the others): lanes split
+// the segment and OR their findings across the group (reading every entry
+// instead of stopping at the first IN gives the same decision); a vertex's
+// lanes share its loop iterations, so the group's shuffles see them all.
+// *undecided is set to 1 (one plain store per workgroup that left a vertex
+// undecided), so the grid needs no cap for a shared counter.
+template <int GL>
+__global__ void k_round_group(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
+                              unsigned long long* undecided) {
+    __shared__ int left;
+    if (threadIdx.x == 0) left = 0;
+    __syncthreads();
+    const int sub = threadIdx.x % GL;
+    const int64_t gpb = blockDim.x / GL;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * gpb + threadIdx.x / GL; v < n;
+         v += static_cast<int64_t>(gridDim.x) * gpb) {
         const uint8_t sv = state[v];
-        if (sv != kUndecided) continue;   // one address: the same value in every lane
-        bool any_in = false, pending = false;
+        if (sv != kUndecided) continue;   // one address: the same value in every lane of the group
+        int any_in = 0, pending = 0;
         const int64_t e = lstart[v + 1];
-        for (int64_t i = lstart[v] + lane; i < e; i += 64) {
+        for (int64_t i = lstart[v] + sub; i < e; i += GL) {
             const uint8_t su = state[lower[i]];
             any_in |= (su == kIn);
             pending |= (su == kUndecided);
         }
-        const bool w_in = __ballot(any_in) != 0ull;
-        const bool w_pending = __ballot(pending) != 0ull;
-        if (lane == 0) {
-            if (w_in) state[v] = kOut;
-            else if (!w_pending) state[v] = kIn;
-            else ++cnt;
+#pragma unroll
+        for (int o = GL / 2; o > 0; o >>= 1) {
+            any_in |= __shfl_xor(any_in, o, 64);
+            pending |= __shfl_xor(pending, o, 64);
+        }
+        if (sub == 0) {
+            if (any_in) state[v] = kOut;
+            else if (!pending) state[v] = kIn;
+            else left = 1;
         }
     }
-    block_fold<0>(undecided, cnt);   // cnt is lane 0's; the other lanes hold 0
+    __syncthreads();
+    if (threadIdx.x == 0 && left) *undecided = 1ull;
 }
 
 __global__ void k_hub_flags_by_rank(const uint32_t* perm, int64_t n, const uint8_t* state, int32_t* hf) {
@@ -257,51 +247,30 @@ __global__ void k_hub_flags_by_rank(const uint32_t* perm, int64_t n, const uint8
 }
 
 // A hub keeps its own cluster; a marked vertex joins the earliest hub among
-// its eligible earlier neighbours.  Cluster id = hubs before it in pi order.
-__global__ void k_assign(int64_t n, const int64_t* lstart, const int32_t* lower, const uint8_t* state,
-                         const int32_t* rank, const int64_t* cid_by_rank, int32_t* map, unsigned int* bad) {
-    GRID_STRIDE(v, n) {
-        int32_t r = -1;
-        if (state[v] == kIn) {
-            r = rank[v];
-        } else if (state[v] == kOut) {
-            int32_t best = INT32_MAX;
-            for (int64_t i = lstart[v], e = lstart[v + 1]; i < e; ++i) {
-                const int32_t u = lower[i];
-                if (state[u] == kIn) best = min(best, rank[u]);
-            }
-            r = best;
-        }
-        if (r < 0 || r >= n) {   // cannot happen once every vertex is decided
-            map[v] = 0;
-            atomicOr(bad, 1u);
-            continue;
-        }
-        map[v] = static_cast<int32_t>(cid_by_rank[r]);
-    }
-}
-
-// k_assign with one wave per vertex (dense levels): lanes take the minimum
-// hub rank over their part of the segment, then the wave reduces it.
-__global__ void k_assign_wave(int64_t n, const int64_t* lstart, const int32_t* lower, const uint8_t* state,
-                              const int32_t* rank, const int64_t* cid_by_rank, int32_t* map, unsigned int* bad) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wpb = blockDim.x >> 6;
-    for (int64_t v = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); v < n;
-         v += static_cast<int64_t>(gridDim.x) * wpb) {
+// its eligible earlier neighbours (GL lanes per vertex take the minimum hub
+// rank over their part of the segment, then the group reduces it).  Cluster
+// id = hubs before it in pi order.
+template <int GL>
+__global__ void k_assign_group(int64_t n, const int64_t* lstart, const int32_t* lower, const uint8_t* state,
+                               const int32_t* rank, const int64_t* cid_by_rank, int32_t* map, unsigned int* bad) {
+    const int sub = threadIdx.x % GL;
+    const int64_t gpb = blockDim.x / GL;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * gpb + threadIdx.x / GL; v < n;
+         v += static_cast<int64_t>(gridDim.x) * gpb) {
         const uint8_t sv = state[v];
         int32_t best = INT32_MAX;
         if (sv == kIn) {
             best = rank[v];
         } else if (sv == kOut) {
             const int64_t e = lstart[v + 1];
-            for (int64_t i = lstart[v] + lane; i < e; i += 64) {
+            for (int64_t i = lstart[v] + sub; i < e; i += GL) {
                 const int32_t u = lower[i];
                 if (state[u] == kIn) best = min(best, rank[u]);
             }
-            for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+#pragma unroll
+            for (int o = GL / 2; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
         }
-        if (lane == 0) {
+        if (sub == 0) {
             if (best < 0 || best >= n) {   // cannot happen once every vertex is decided
                 map[v] = 0;
                 atomicOr(bad, 1u);
@@ -1087,7 +1056,7 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     DevBuf<uint8_t> state(c, n);
     fill(c, state.p, n, 0);
     // three rounds per host check (a round over decided vertices changes
-    // nothing, and the R-MAT levels take 2-4): the count read back is the
+    // nothing, and the R-MAT levels take 2-4): the flag read back is the
     // last round's
     constexpr int kRoundsPerCheck = 3;
     for (int64_t round = 0;; round += kRoundsPerCheck) {
@@ -1095,11 +1064,11 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
         for (int r = 0; r < kRoundsPerCheck; ++r) {
             GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
             if (dense)
-                hipLaunchKernelGGL(k_round_wave, grid_reduce(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
+                hipLaunchKernelGGL(k_round_group<64>, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
                                    lstart.p, lower.p, state.p, scratch_u64(c, 1));
             else
-                hipLaunchKernelGGL(k_round, grid_reduce(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p,
-                                   state.p, scratch_u64(c, 1));
+                hipLaunchKernelGGL(k_round_group<kSparseGroup>, grid_for(n, kThreads / kSparseGroup), dim3(kThreads),
+                                   0, c->stream, n, lstart.p, lower.p, state.p, scratch_u64(c, 1));
             GOSH_HIP(hipGetLastError());
         }
         if (read_u64(c, scratch_u64(c, 1)) == 0) break;
@@ -1116,11 +1085,11 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     hf.reset();
     L.map = static_cast<int32_t*>(c->alloc(sizeof(int32_t) * n));
     if (dense)
-        hipLaunchKernelGGL(k_assign_wave, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
+        hipLaunchKernelGGL(k_assign_group<64>, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n, lstart.p,
                            lower.p, state.p, rank_p, cid.p, L.map, bad);
     else
-        hipLaunchKernelGGL(k_assign, grid_for(n), dim3(kThreads), 0, c->stream, n, lstart.p, lower.p, state.p,
-                           rank_p, cid.p, L.map, bad);
+        hipLaunchKernelGGL(k_assign_group<kSparseGroup>, grid_for(n, kThreads / kSparseGroup), dim3(kThreads), 0,
+                           c->stream, n, lstart.p, lower.p, state.p, rank_p, cid.p, L.map, bad);
     GOSH_HIP(hipGetLastError());
     return n_next;
 }
