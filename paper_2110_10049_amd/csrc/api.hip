@@ -161,6 +161,7 @@ gosh_status gosh_ctx_create(int device, uint64_t seed, void* hip_stream, uint64_
         GOSH_HIP(hipMemsetAsync(c->scratch, 0, 4096, c->stream));
         GOSH_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sizeof(int64_t) * Ctx::kPinnedSlots,
                                hipHostMallocDefault));
+        GOSH_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->pinned_dev), c->pinned, 0));
         gosh::batched_noalloc_init(device);
     });
     if (st != GOSH_OK) {

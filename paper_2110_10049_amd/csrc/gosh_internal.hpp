@@ -68,6 +68,7 @@ struct Ctx {
     // pinned host slots for single values read back from the device (a copy
     // into pageable memory would block the host on its own)
     int64_t* pinned = nullptr; // kPinnedSlots slots
+    int64_t* pinned_dev = nullptr; // the same slots as kernels address them (they write scan totals there)
     static constexpr int kPinnedSlots = 64;
     // batched-training autotune cache: key -> (mode, blocks per CU, chunk iterations)
     std::map<std::string, std::array<int, 3>> tune;

@@ -101,10 +101,12 @@ __device__ __forceinline__ void store_run(int64_t* out, int64_t start, int64_t n
 }
 
 // Scans one tile per block (blocked arrangement: thread t owns items
-// [t*kScanItems, (t+1)*kScanItems) of the tile), adding prefix[block].
+// [t*kScanItems, (t+1)*kScanItems) of the tile), adding prefix[block].  With
+// all_out set, the thread holding item n-1 writes the reduction of all n
+// inputs there (a pinned host slot: no copy back).
 template <class T, ScanOp OP>
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const T* in, int64_t* out, int64_t n,
-                                                             const int64_t* prefix, int inclusive) {
+                                                             const int64_t* prefix, int inclusive, int64_t* all_out) {
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     const int64_t start = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
     int64_t v[kScanItems];
@@ -120,17 +122,18 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const T* in, int64_t
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t nxt = apply<OP>(run, v[i]);
         r[i] = inclusive ? nxt : run;
+        if (all_out && start + i == n - 1) *all_out = nxt;
         run = nxt;
     }
     store_run(out, start, n, r);
 }
 
 template <class T, ScanOp OP>
-void scan_launch(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive) {
+void scan_launch(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int64_t* total) {
     const int64_t nb = ceil_div(n, kScanTile);
     if (nb == 1) {
         hipLaunchKernelGGL((k_tile_scan<T, OP>), dim3(1), dim3(kScanThreads), 0, c->stream, in, out,
-                           n, nullptr, inclusive ? 1 : 0);
+                           n, nullptr, inclusive ? 1 : 0, total);
         GOSH_HIP(hipGetLastError());
         return;
     }
@@ -138,9 +141,9 @@ void scan_launch(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive) {
     hipLaunchKernelGGL((k_tile_reduce<T, OP>), dim3(nb), dim3(kScanThreads), 0, c->stream, in, n,
                        part.p);
     GOSH_HIP(hipGetLastError());
-    scan_launch<int64_t, OP>(c, part.p, part.p, nb, false);
+    scan_launch<int64_t, OP>(c, part.p, part.p, nb, false, nullptr);
     hipLaunchKernelGGL((k_tile_scan<T, OP>), dim3(nb), dim3(kScanThreads), 0, c->stream, in, out, n,
-                       part.p, inclusive ? 1 : 0);
+                       part.p, inclusive ? 1 : 0, total);
     GOSH_HIP(hipGetLastError());
 }
 
@@ -150,17 +153,12 @@ void scan_impl(Ctx* c, const T* in, int64_t* out, int64_t n, bool inclusive, int
         if (total_host) *total_host = 0;
         return;
     }
-    // The last input is fetched before the scan because `out` may alias `in`;
-    // both values land in the context's pinned slots, so the host waits once.
-    T* last_in = reinterpret_cast<T*>(c->pinned);
-    int64_t* last_out = c->pinned + 1;
-    if (total_host && !inclusive)
-        GOSH_HIP(hipMemcpyAsync(last_in, in + n - 1, sizeof(T), hipMemcpyDeviceToHost, c->stream));
-    scan_launch<T, OP>(c, in, out, n, inclusive);
+    // The scan kernel writes the total into a pinned slot of the context
+    // (no copy kernel), and the host waits once.
+    scan_launch<T, OP>(c, in, out, n, inclusive, total_host ? c->pinned_dev + 1 : nullptr);
     if (total_host) {
-        GOSH_HIP(hipMemcpyAsync(last_out, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
         GOSH_HIP(hipStreamSynchronize(c->stream));
-        *total_host = inclusive ? *last_out : apply<OP>(*last_out, static_cast<int64_t>(*last_in));
+        *total_host = c->pinned[1];
     }
 }
 

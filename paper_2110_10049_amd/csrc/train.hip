@@ -179,17 +179,24 @@ __global__ void k_draw(TrainParams P, int32_t* out) {
 // Adds the UpdateEmbed calls of `epochs` epochs without self-negatives:
 // one positive per vertex with neighbours plus k negatives per vertex
 // (negatives equal to the source are subtracted by the training kernel).
+// One add per workgroup (a per-wave add put thousands of atomics on one
+// counter); blocks of 256 threads.
 template <class Off>
-__global__ void k_add_updates(const Off* off, int64_t n, int k, int epochs, unsigned long long* p) {
+__global__ __launch_bounds__(256) void k_add_updates(const Off* off, int64_t n, int k, int epochs,
+                                                     unsigned long long* p) {
+    __shared__ unsigned long long part[4];
     unsigned long long cnt = 0;
     for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
          v += static_cast<int64_t>(gridDim.x) * blockDim.x)
         cnt += (off[v + 1] != off[v]) ? 1ull : 0ull;
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    unsigned long long add = ((threadIdx.x & 63) == 0) ? cnt * static_cast<unsigned long long>(epochs) : 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        add += static_cast<unsigned long long>(k) * static_cast<unsigned long long>(n) * epochs;
-    if (add) atomicAdd(p, add);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long add = (part[0] + part[1] + part[2] + part[3]) * static_cast<unsigned long long>(epochs);
+        if (blockIdx.x == 0) add += static_cast<unsigned long long>(k) * static_cast<unsigned long long>(n) * epochs;
+        if (add) atomicAdd(p, add);
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -441,7 +448,7 @@ void train_level(Ctx* c, const Level& L, int32_t level, void* emb, gosh_dtype dt
     }
     }
     if (updates_dev) {
-        const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(L.n, 256), 1024));
+        const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.n, 256), 512)));
         auto* cnt = reinterpret_cast<unsigned long long*>(updates_dev);
         if (L.off64)
             hipLaunchKernelGGL(k_add_updates<int64_t>, dim3(blocks), dim3(256), 0, c->stream,
