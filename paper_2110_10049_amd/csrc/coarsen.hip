@@ -125,9 +125,14 @@ constexpr int64_t kLowerTile = int64_t(kThreads) * kLowerItems;
 constexpr int kLowerWords = static_cast<int>(kLowerTile / 64);   // 64 words per tile
 
 // rl[v] = rank of v in pi, with bit 31 set when v is light: the keep test
-// then takes one random lookup per entry instead of two
-__global__ void k_pack_rank_light(const int32_t* rank, const uint8_t* light, int64_t n, uint32_t* rl) {
-    GRID_STRIDE(v, n) rl[v] = static_cast<uint32_t>(rank[v]) | (light[v] ? 0x80000000u : 0u);
+// then takes one random lookup per entry instead of two.  Also starts every
+// vertex of the hub rounds undecided.
+__global__ void k_pack_rank_light(const int32_t* rank, const uint8_t* light, int64_t n, uint32_t* rl,
+                                  uint8_t* state) {
+    GRID_STRIDE(v, n) {
+        rl[v] = static_cast<uint32_t>(rank[v]) | (light[v] ? 0x80000000u : 0u);
+        state[v] = kUndecided;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_lower_bits(const int32_t* src, const int32_t* idx, int64_t nnz,
@@ -136,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_lower_bits(const int32_t* src, con
     __shared__ int wc[kLowerWords];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kLowerTile;
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_cnt[gridDim.x] = 0;   // the total's slot of the scan
 #pragma unroll 4
     for (int r = 0; r < kLowerItems; ++r) {
         const int64_t p = base + r * kThreads + threadIdx.x;
@@ -207,12 +213,14 @@ constexpr int kSparseGroup = 8;   // lanes per vertex in the rounds and the assi
 // instead of stopping at the first IN gives the same decision); a vertex's
 // lanes share its loop iterations, so the group's shuffles see them all.
 // *undecided is set to 1 (one plain store per workgroup that left a vertex
-// undecided), so the grid needs no cap for a shared counter.
+// undecided), so the grid needs no cap for a shared counter; *next_flag, the
+// next round's, is cleared here (it is nobody else's in this launch).
 template <int GL>
 __global__ void k_round_group(int64_t n, const int64_t* lstart, const int32_t* lower, uint8_t* state,
-                              unsigned long long* undecided) {
+                              unsigned long long* undecided, unsigned long long* next_flag) {
     __shared__ int left;
     if (threadIdx.x == 0) left = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next_flag = 0ull;
     __syncthreads();
     const int sub = threadIdx.x % GL;
     const int64_t gpb = blockDim.x / GL;
@@ -1026,6 +1034,7 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
     const int64_t n = L.n, nnz = L.nnz;
     DevBuf<int32_t> lower(c, std::max<int64_t>(nnz, 1));
     DevBuf<int64_t> lstart(c, n + 1);
+    DevBuf<uint8_t> state(c, n);   // hub-round states, all undecided to start
     if (nnz > 0) {
         const int64_t tiles = ceil_div(nnz, kLowerTile);
         const int64_t words = ceil_div(nnz, int64_t(64));
@@ -1033,8 +1042,8 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
         DevBuf<uint16_t> wpre(c, words);
         DevBuf<int64_t> tile(c, tiles + 1);
         DevBuf<uint32_t> rl(c, n);
-        fill(c, tile.p + tiles, 1, 0);
-        hipLaunchKernelGGL(k_pack_rank_light, grid_for(n), dim3(kThreads), 0, c->stream, rank_p, light_p, n, rl.p);
+        hipLaunchKernelGGL(k_pack_rank_light, grid_for(n), dim3(kThreads), 0, c->stream, rank_p, light_p, n, rl.p,
+                           state.p);
         GOSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_lower_bits, dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, c->stream, src, idx,
                            nnz, rl.p, bits.p, wpre.p, tile.p);
@@ -1048,30 +1057,32 @@ int64_t map_exact(Ctx* c, Level& L, const Off* off, const int32_t* idx, const in
         GOSH_HIP(hipGetLastError());
     } else {
         fill(c, lstart.p, n + 1, 0);
+        fill(c, state.p, n, 0);
     }
 
     // hub selection rounds; each round decides at least the earliest
     // undecided vertex, so the loop ends; dense levels (average degree >= 64)
-    // scan each segment with a whole wave
-    DevBuf<uint8_t> state(c, n);
-    fill(c, state.p, n, 0);
-    // three rounds per host check (a round over decided vertices changes
-    // nothing, and the R-MAT levels take 2-4): the flag read back is the
-    // last round's
+    // scan each segment with a whole wave.  Three rounds per host check (a
+    // round over decided vertices changes nothing, and the R-MAT levels take
+    // 2-4); round g sets flag g mod 2 and clears the other for round g + 1,
+    // so only the first flag needs a fill, and the flag read back is the
+    // last round's.
+    unsigned long long* flag[2] = {scratch_u64(c, 1), scratch_u64(c, 5)};
+    GOSH_HIP(hipMemsetAsync(flag[0], 0, 8, c->stream));
     constexpr int kRoundsPerCheck = 3;
     for (int64_t round = 0;; round += kRoundsPerCheck) {
         GOSH_REQUIRE(round <= n + kRoundsPerCheck, GOSH_E_DEVICE, "coarsening rounds did not converge");
         for (int r = 0; r < kRoundsPerCheck; ++r) {
-            GOSH_HIP(hipMemsetAsync(scratch_u64(c, 1), 0, 8, c->stream));
+            const int g = static_cast<int>((round + r) & 1);
             if (dense)
                 hipLaunchKernelGGL(k_round_group<64>, grid_for(n, kThreads / 64), dim3(kThreads), 0, c->stream, n,
-                                   lstart.p, lower.p, state.p, scratch_u64(c, 1));
+                                   lstart.p, lower.p, state.p, flag[g], flag[g ^ 1]);
             else
                 hipLaunchKernelGGL(k_round_group<kSparseGroup>, grid_for(n, kThreads / kSparseGroup), dim3(kThreads),
-                                   0, c->stream, n, lstart.p, lower.p, state.p, scratch_u64(c, 1));
+                                   0, c->stream, n, lstart.p, lower.p, state.p, flag[g], flag[g ^ 1]);
             GOSH_HIP(hipGetLastError());
         }
-        if (read_u64(c, scratch_u64(c, 1)) == 0) break;
+        if (read_u64(c, flag[(round + kRoundsPerCheck - 1) & 1]) == 0) break;
     }
 
     // cluster ids: hubs counted in pi order
