@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cstring>
 
 #include "device_util.hpp"
@@ -879,7 +880,12 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
     GOSH_HIP(hipMemcpyAsync(ckey.p, map, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
     hipLaunchKernelGGL(k_iota_u32, grid_for(n), dim3(kThreads), 0, c->stream, mem.p, n);
     GOSH_HIP(hipGetLastError());
-    radix_sort_u32(c, ckey.p, ckey_tmp.p, mem.p, mem_tmp.p, n, bb);
+    bool in_tmp = false;   // sorted into the _tmp buffers: swap instead of copying back
+    radix_sort_u32(c, ckey.p, ckey_tmp.p, mem.p, mem_tmp.p, n, bb, &in_tmp);
+    if (in_tmp) {
+        std::swap(ckey, ckey_tmp);
+        std::swap(mem, mem_tmp);
+    }
     ckey_tmp.reset();
     mem_tmp.reset();
     DevBuf<int64_t> E(c, n);
@@ -1159,8 +1165,10 @@ void coarsen_one(Ctx* c, Level& L, Level& next, DevBuf<int32_t>* src_in) {
                        reinterpret_cast<const unsigned long long*>(scratch_u64(c, 0)), key.p, perm.p);
     GOSH_HIP(hipGetLastError());
     // deg <= nnz/1 < 2^bits_for(max(n-1, nnz)) bounds maxdeg - deg
+    bool in_tmp = false;   // sorted into the _tmp buffers: swap instead of copying back
     radix_sort_u32(c, key.p, key_tmp.p, perm.p, perm_tmp.p, n,
-                   bits_for(static_cast<uint64_t>(std::min<int64_t>(std::max<int64_t>(n - 1, 0), nnz))));
+                   bits_for(static_cast<uint64_t>(std::min<int64_t>(std::max<int64_t>(n - 1, 0), nnz))), &in_tmp);
+    if (in_tmp) std::swap(perm, perm_tmp);
     key_tmp.reset();
     perm_tmp.reset();
     key.reset();

@@ -295,7 +295,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys, K
 
 template <class K, bool VALS, int ITEMS>
 void radix_sort_impl(Ctx* c, K* keys, K* keys_tmp, uint32_t* vals, uint32_t* vals_tmp, int64_t n,
-                     int bits) {
+                     int bits, bool* in_tmp) {
+    if (in_tmp) *in_tmp = false;
     if (n <= 1 || bits <= 0) return;
     const int64_t nb = ceil_div(n, static_cast<int64_t>(kSortThreads) * ITEMS);
     DevBuf<int64_t> hist(c, static_cast<size_t>(nb) * kRadix);
@@ -314,7 +315,9 @@ void radix_sort_impl(Ctx* c, K* keys, K* keys_tmp, uint32_t* vals, uint32_t* val
         std::swap(src, dst);
         std::swap(vsrc, vdst);
     }
-    if (src != keys) {
+    if (src != keys && in_tmp) {
+        *in_tmp = true;   // the caller takes the result from the _tmp buffers
+    } else if (src != keys) {
         GOSH_HIP(hipMemcpyAsync(keys, src, sizeof(K) * n, hipMemcpyDeviceToDevice, c->stream));
         if (VALS)
             GOSH_HIP(hipMemcpyAsync(vals, vsrc, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
@@ -339,19 +342,19 @@ void scan_i32_to_i64(Ctx* c, const int32_t* in, int64_t* out, int64_t n, int64_t
 constexpr int64_t kLargeSort = int64_t(4) << 20;
 
 void radix_sort_u32(Ctx* c, uint32_t* keys, uint32_t* keys_tmp, uint32_t* vals,
-                    uint32_t* vals_tmp, int64_t n, int bits) {
+                    uint32_t* vals_tmp, int64_t n, int bits, bool* in_tmp) {
     if (n >= kLargeSort) {
-        if (vals) radix_sort_impl<uint32_t, true, 16>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
-        else radix_sort_impl<uint32_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+        if (vals) radix_sort_impl<uint32_t, true, 16>(c, keys, keys_tmp, vals, vals_tmp, n, bits, in_tmp);
+        else radix_sort_impl<uint32_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits, in_tmp);
     } else {
-        if (vals) radix_sort_impl<uint32_t, true, 4>(c, keys, keys_tmp, vals, vals_tmp, n, bits);
-        else radix_sort_impl<uint32_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+        if (vals) radix_sort_impl<uint32_t, true, 4>(c, keys, keys_tmp, vals, vals_tmp, n, bits, in_tmp);
+        else radix_sort_impl<uint32_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits, in_tmp);
     }
 }
 
-void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits) {
-    if (n >= kLargeSort) radix_sort_impl<uint64_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
-    else radix_sort_impl<uint64_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits);
+void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits, bool* in_tmp) {
+    if (n >= kLargeSort) radix_sort_impl<uint64_t, false, 16>(c, keys, keys_tmp, nullptr, nullptr, n, bits, in_tmp);
+    else radix_sort_impl<uint64_t, false, 4>(c, keys, keys_tmp, nullptr, nullptr, n, bits, in_tmp);
 }
 
 }  // namespace gosh

@@ -18,9 +18,11 @@ void scan_i32_to_i64(Ctx* c, const int32_t* in, int64_t* out, int64_t n, int64_t
 
 // Stable LSD radix sort on bits [0, bits) of the keys, 8 bits per pass.
 // Sorted keys (and values, if vals != nullptr) end up in `keys`/`vals`;
-// `keys_tmp`/`vals_tmp` are scratch of the same length.
+// `keys_tmp`/`vals_tmp` are scratch of the same length.  With in_tmp set,
+// an odd pass count leaves them in `keys_tmp`/`vals_tmp` instead (no copy
+// back) and *in_tmp says so.
 void radix_sort_u32(Ctx* c, uint32_t* keys, uint32_t* keys_tmp, uint32_t* vals,
-                    uint32_t* vals_tmp, int64_t n, int bits);
-void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits);
+                    uint32_t* vals_tmp, int64_t n, int bits, bool* in_tmp = nullptr);
+void radix_sort_u64(Ctx* c, uint64_t* keys, uint64_t* keys_tmp, int64_t n, int bits, bool* in_tmp = nullptr);
 
 }  // namespace gosh
