@@ -591,8 +591,8 @@ __global__ __launch_bounds__(64 * kSegWaves) void k_dedup_small(const int64_t* s
 // a giant's index among the giants in the low half (at most n_next < 2^31, so
 // it never carries) and its first chunk in the high half.
 __global__ void k_giant_flags(const int64_t* segstart, int64_t n_next, int64_t* pk) {
-    GRID_STRIDE(c, n_next) {
-        const int64_t len = segstart[c + 1] - segstart[c];
+    GRID_STRIDE(c, n_next + 1) {   // pk[n_next] = 0: the scan leaves the packed total there
+        const int64_t len = c < n_next ? segstart[c + 1] - segstart[c] : 0;
         pk[c] = len > kSegSmall ? 1 + (ceil_div(len, kGiantChunk) << 32) : 0;
     }
 }
@@ -600,6 +600,9 @@ __device__ __forceinline__ int64_t giant_index(int64_t pre) { return pre & 0xFFF
 __device__ __forceinline__ int64_t first_chunk(int64_t pre) { return pre >> 32; }
 
 constexpr int kGiantThreads = 1024;
+constexpr int64_t kGiantBlocks = 1024;        // workgroups of the giant zero / emit launches, at most
+constexpr int64_t kGiantChunkBlocks = 4096;   // workgroups of the chunk launch, at most
+constexpr int64_t kGiantBoundWords = int64_t(256) << 20;   // bitmap words sized by the bound, at most (1 GiB)
 
 // One workgroup per chunk of a giant segment: the chunk's clusters OR-ed
 // into the workgroup's LDS bitmap, then its non-zero words OR-ed into the
@@ -607,12 +610,15 @@ constexpr int kGiantThreads = 1024;
 // belongs to the last cluster c whose first chunk is <= t (clusters without
 // chunks share their first chunk with the next cluster, so the last one is a
 // giant).
+// The chunk count is read from the device (pre[n_next], the packed total),
+// so the host need not wait for it; the grid is an upper bound.
 __global__ __launch_bounds__(kGiantThreads) void k_giant_chunks(const int64_t* segstart, int64_t n_next,
-                                                                const int64_t* pre, int64_t chunks, int W,
-                                                                const uint32_t* raw, uint32_t* gbm) {
+                                                                const int64_t* pre, int W, const uint32_t* raw,
+                                                                uint32_t* gbm) {
     extern __shared__ uint32_t seg_bitmaps[];
     __shared__ uint32_t red[2][kGiantThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t chunks = first_chunk(pre[n_next]);
     for (int64_t t = blockIdx.x; t < chunks; t += gridDim.x) {
         int64_t lo = 0, hi = n_next;
         while (hi - lo > 1) {
@@ -687,9 +693,12 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
 }
 
 // One block per giant (cluster gc[g]): count of its global bitmap (out ==
-// nullptr) or its ids written ascending from indices[offs[c]].
-__global__ __launch_bounds__(kGiantThreads) void k_giant_emit(const int32_t* gc, int64_t G, int W, const uint32_t* gbm,
-                                                              int32_t* cnt, const int64_t* offs, int32_t* indices) {
+// nullptr) or its ids written ascending from indices[offs[c]].  The giant
+// count is read from the device (*packed, the total of the giant scan).
+__global__ __launch_bounds__(kGiantThreads) void k_giant_emit(const int32_t* gc, const int64_t* packed, int W,
+                                                              const uint32_t* gbm, int32_t* cnt, const int64_t* offs,
+                                                              int32_t* indices) {
+    const int64_t G = giant_index(*packed);
     for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
         const int64_t cl = gc[g];
         const uint32_t* bm = gbm + g * static_cast<int64_t>(W);
@@ -714,6 +723,14 @@ __global__ __launch_bounds__(kGiantThreads) void k_giant_emit(const int32_t* gc,
 }
 
 // gc[giant index of c] = c for every giant
+// Clears the giants' global bitmaps (rows 0 .. G-1 of W words, G read from
+// the device).
+__global__ void k_giant_zero(const int64_t* packed, int W, uint32_t* gbm) {
+    const int64_t G = giant_index(*packed);
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x)
+        for (int w = threadIdx.x; w < W; w += blockDim.x) gbm[g * W + w] = 0u;
+}
+
 __global__ void k_giant_list(const int64_t* segstart, const int64_t* pre, int64_t n_next, int32_t* gc) {
     GRID_STRIDE(c, n_next) {
         if (segstart[c + 1] - segstart[c] > kSegSmall) gc[giant_index(pre[c])] = static_cast<int32_t>(c);
@@ -915,13 +932,25 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
     mem.reset();
     ckey.reset();
 
-    // giant segments: their count and chunks from one packed scan
-    DevBuf<int64_t> pre(c, n_next);
-    hipLaunchKernelGGL(k_giant_flags, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, n_next, pre.p);
+    // giant segments: their count and chunks from one packed scan, whose
+    // total stays on the device (pre[n_next]); the host sizes the giant
+    // buffers and grids by upper bounds (a giant has more than kSegSmall
+    // entries) instead of waiting for it, unless the bounds' bitmaps would
+    // be too large, when it reads the total back
+    DevBuf<int64_t> pre(c, n_next + 1);
+    hipLaunchKernelGGL(k_giant_flags, grid_for(n_next + 1), dim3(kThreads), 0, c->stream, segstart.p, n_next, pre.p);
     GOSH_HIP(hipGetLastError());
-    int64_t packed = 0;
-    scan_i64(c, pre.p, pre.p, n_next, false, ScanOp::Sum, &packed);
-    const int64_t G = packed & 0xFFFFFFFFll, chunks = packed >> 32;
+    int64_t G = std::min<int64_t>(n_next, nnz / (kSegSmall + 1));
+    int64_t chunks = nnz / kGiantChunk + G;
+    if (G * W > kGiantBoundWords) {
+        int64_t packed = 0;
+        scan_i64(c, pre.p, pre.p, n_next + 1, false, ScanOp::Sum, &packed);
+        G = packed & 0xFFFFFFFFll;
+        chunks = packed >> 32;
+    } else {
+        scan_i64(c, pre.p, pre.p, n_next + 1, false, ScanOp::Sum, nullptr);
+    }
+    const int64_t* packed_dev = pre.p + n_next;
 
     DevBuf<int32_t> cnt(c, n_next);
     // as many workgroups as fit on the device at once: each wave clears its
@@ -938,25 +967,29 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
     hipLaunchKernelGGL(k_dedup_small, dim3(static_cast<unsigned>(std::max<int64_t>(dblocks, 1))),
                        dim3(64 * kSegWaves), lds, c->stream, segstart.p, n_next, static_cast<int>(W), raw.p, cnt.p);
     GOSH_HIP(hipGetLastError());
+    // G and chunks: the exact counts or upper bounds (the kernels read the
+    // exact ones from packed_dev)
     DevBuf<int32_t> gc(c, std::max<int64_t>(G, 1));
     DevBuf<uint32_t> gbm(c, std::max<int64_t>(G * W, 1));
+    const unsigned gblocks = static_cast<unsigned>(std::min<int64_t>(G, kGiantBlocks));
     if (G > 0) {
-        GOSH_HIP(hipMemsetAsync(gbm.p, 0, sizeof(uint32_t) * G * W, c->stream));
+        hipLaunchKernelGGL(k_giant_zero, dim3(gblocks), dim3(kThreads), 0, c->stream, packed_dev,
+                           static_cast<int>(W), gbm.p);
+        GOSH_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_giant_list, grid_for(n_next), dim3(kThreads), 0, c->stream, segstart.p, pre.p, n_next,
                            gc.p);
         GOSH_HIP(hipGetLastError());
         const size_t glds = sizeof(uint32_t) * static_cast<size_t>(W);
         GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_giant_chunks),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(glds)));
-        hipLaunchKernelGGL(k_giant_chunks, dim3(static_cast<unsigned>(std::min<int64_t>(chunks, 65536))),
-                           dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, pre.p, chunks,
-                           static_cast<int>(W), raw.p, gbm.p);
+        hipLaunchKernelGGL(k_giant_chunks, dim3(static_cast<unsigned>(std::min<int64_t>(chunks, kGiantChunkBlocks))),
+                           dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, pre.p, static_cast<int>(W),
+                           raw.p, gbm.p);
         GOSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_giant_emit, dim3(static_cast<unsigned>(std::min<int64_t>(G, 4096))), dim3(kGiantThreads), 0,
-                           c->stream, gc.p, G, static_cast<int>(W), gbm.p, cnt.p, nullptr, nullptr);
+        hipLaunchKernelGGL(k_giant_emit, dim3(gblocks), dim3(kGiantThreads), 0, c->stream, gc.p, packed_dev,
+                           static_cast<int>(W), gbm.p, cnt.p, nullptr, nullptr);
         GOSH_HIP(hipGetLastError());
     }
-    pre.reset();
 
     // offsets from the distinct counts, then the rows
     DevBuf<int64_t> offs(c, n_next);
@@ -975,8 +1008,8 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
                        n_next, cnt.p, offs.p, raw.p, indices);
     GOSH_HIP(hipGetLastError());
     if (G > 0) {
-        hipLaunchKernelGGL(k_giant_emit, dim3(static_cast<unsigned>(std::min<int64_t>(G, 4096))), dim3(kGiantThreads), 0,
-                           c->stream, gc.p, G, static_cast<int>(W), gbm.p, cnt.p, offs.p, indices);
+        hipLaunchKernelGGL(k_giant_emit, dim3(gblocks), dim3(kGiantThreads), 0, c->stream, gc.p, packed_dev,
+                           static_cast<int>(W), gbm.p, cnt.p, offs.p, indices);
         GOSH_HIP(hipGetLastError());
     }
     *off_out = offsets;
