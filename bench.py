@@ -120,6 +120,8 @@ def parse():
                     help="MIN,MAX,FACTOR: group the visits of hot positives (hubs of degree >= FACTOR x average) on "
                          "levels with MIN <= n <= MAX (MAX 0: off)")
     ap.add_argument("--no-auc", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-prolongation comparison of the default workload")
     ap.add_argument("--no-loss", action="store_true", help="skip the untimed running-loss passes")
     ap.add_argument("--lds-levels", type=int, default=0,
                     help="train levels / batched jobs of at most this many vertices whose rows fit in LDS inside "
@@ -914,6 +916,9 @@ def main_workload(a):
         del r_e
         log(f"auc {auc} ({time.time() - t:.1f}s)")
         out["auc"] = auc
+        if a.workload == "rmat20" and d == 128 and f32 is not None and not a.no_learned:
+            out["learned_prolongation"] = learned_vs_copy(ctx, g, EmbedConfig, init_for, pairs, auc["fp32"],
+                                                          f32["ms_per_step"], d, k, p, lr, threshold, seeds)
     if not a.no_loss:
         # running loss (Section 2's objective over each epoch's updates), one untimed pass per dtype
         loss = {}
@@ -948,6 +953,63 @@ def main_workload(a):
         log(f"cpu baseline {upd / dt / 1e6:.2f} M edge-samples/s on {cores} threads, "
             f"{upd1 / dt1 / 1e6:.2f} M/s on one")
     print(json.dumps(out), flush=True)
+
+
+def learned_vs_copy(ctx, g, EmbedConfig, init_for, pairs, fp32_auc, fp32_ms, d, k, p, lr, threshold, seeds,
+                    budgets=(75, 150), hidden=256, steps=2000):
+    """The learned prolongation against FP32 + copy on the benchmark's graph:
+    a network (d = 128, 256 GELU units) is trained on the (coarse, fine)
+    pairs of every level of a BF16 copy run on the scale-18 R-MAT train
+    graph; the scale-20 graph is then embedded in BF16 with the network and
+    with copy at a few epoch budgets (whole passes: coarsening, training and
+    prolongation, 3 timed after 1 untimed) and scored on the benchmark's
+    evaluation pairs.  equal_auc: the smallest budget whose learned AUC is
+    within 0.01 of FP32 + copy at the full 600 epochs, and its time against
+    that run's."""
+    import torch
+
+    from paper_2110_10049_amd import gosh as G
+    from paper_2110_10049_amd.driver import embed
+    from synth import init_rows, rmat_csr, split_edges
+    from synth.linkpred import auc_on_pairs
+
+    t0 = time.time()
+    off, idx = rmat_csr(18, 16, seeds["graph"])
+    sp18 = split_edges(off, idx, seeds["split"])
+    g18 = G.CSR.from_numpy(sp18.offsets, sp18.indices)
+    cfg18 = EmbedConfig(d=d, epochs=600, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=threshold)
+    res18 = embed(ctx, g18, cfg18, lambda n, dd: torch.from_numpy(init_rows(n, dd, seeds["init"])).cuda()
+                  .to(torch.bfloat16), keep_levels=True)
+    lv18 = res18.levels
+    sources = [(lv18, i, res18.trained[i + 1], res18.trained[i]) for i in range(lv18.count() - 1)]
+    net = G.Mlp(ctx, d, hidden)
+    net.train(sources, steps, 1024, 1e-3, tag=7, losses=False)
+    torch.cuda.synchronize()
+    log(f"learned prolongation: network trained on scale 18 ({time.time() - t0:.1f}s)")
+    runs = []
+    for e in budgets:
+        for name, m in (("bf16+learned", net), ("bf16+copy", None)):
+            cfg = EmbedConfig(d=d, epochs=e, p=p, lr=lr, k=k, dtype=torch.bfloat16, threshold=threshold)
+            embed(ctx, g, cfg, init_for(torch.bfloat16), mlp=m)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                res = embed(ctx, g, cfg, init_for(torch.bfloat16), mlp=m)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / 3
+            upd = int(res.updates.item())
+            runs.append({"run": name, "epochs": e, "auc": round(auc_on_pairs(res.emb.float().cpu().numpy(), pairs), 4),
+                         "ms_per_step": round(sec * 1e3, 3), "edge_samples_per_s": round(upd / sec, 1)})
+            log(f"learned prolongation: {runs[-1]}")
+    ok = [r for r in runs if r["run"] == "bf16+learned" and r["auc"] >= fp32_auc - 0.01]
+    best = min(ok, key=lambda r: r["epochs"]) if ok else None
+    return {"network": {"trained_on": "all level pairs of a BF16 copy run on the R-MAT scale-18 train graph",
+                        "hidden": hidden, "adam_steps": steps, "batch": 1024},
+            "reference": {"run": "fp32+copy", "epochs": 600, "auc": fp32_auc, "ms_per_step": round(fp32_ms, 3)},
+            "runs": runs,
+            "equal_auc": {"bf16_learned_at": best,
+                          "time_ratio_fp32copy_over_bf16learned": round(fp32_ms / best["ms_per_step"], 3)
+                          if best else None}}
 
 
 def scale22_roofline(ctx, d, k, lr, seeds):
