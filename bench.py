@@ -27,8 +27,11 @@ scale-22 graph whose rows do not.  Also reported: every level's time,
 updates and edge-samples/s, the coarsening's time, edges/s and fraction of
 its algorithmic bytes, link-prediction AUC of both dtypes against the FP64
 oracle's stored result for the same seeds and evaluation pairs, the AUC of
-the degree product alone, AUC in the paper's epoch unit (|E| updates), and
-the running loss of every level's last epoch beside the oracle's.
+the degree product alone, AUC in the paper's epoch unit (|E| updates), the
+running loss of every level's last epoch beside the oracle's, and
+(learned_prolongation) BF16 with the learned prolongation at small epoch
+budgets against FP32 + copy at 600 epochs: AUC, time and the time ratio at
+equal AUC.
 cpu_baseline: the FP64 oracle's trainer on the level-0 graph with each
 epoch's sources over all host cores (OpenMP, Hogwild), the single-threaded
 sequential oracle beside it.
