@@ -956,12 +956,23 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
     // as many workgroups as fit on the device at once: each wave clears its
     // bitmap once and then takes segment after segment
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(W + ceil_div(W, 32)) * kSegWaves;
-    GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dedup_small),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    int per_cu = 0, cus = 0;
-    GOSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_dedup_small),
-                                                          64 * kSegWaves, lds));
-    GOSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    // launch facts are queried once per context (each query is a host call
+    // on the critical path right after the level's count was read back)
+    if (!c->seg_lds_set) {
+        const size_t lds_max = sizeof(uint32_t) * static_cast<size_t>(kSegMaxWords + kSegMaxWords / 32) * kSegWaves;
+        GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dedup_small),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_max)));
+        GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_giant_chunks),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(sizeof(uint32_t) * kSegMaxWords)));
+        GOSH_HIP(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->seg_lds_set = true;
+    }
+    int& per_cu = c->dedup_per_cu[lds];
+    if (per_cu == 0)
+        GOSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_dedup_small),
+                                                              64 * kSegWaves, lds));
+    const int cus = c->cus;
     const int64_t dblocks = std::min<int64_t>(ceil_div(n_next, kSegWaves),
                                               static_cast<int64_t>(std::max(per_cu, 1)) * std::max(cus, 1));
     hipLaunchKernelGGL(k_dedup_small, dim3(static_cast<unsigned>(std::max<int64_t>(dblocks, 1))),
@@ -980,8 +991,6 @@ int64_t build_coarse_seg(Ctx* c, const Off* off, const int32_t* src, const int32
                            gc.p);
         GOSH_HIP(hipGetLastError());
         const size_t glds = sizeof(uint32_t) * static_cast<size_t>(W);
-        GOSH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_giant_chunks),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(glds)));
         hipLaunchKernelGGL(k_giant_chunks, dim3(static_cast<unsigned>(std::min<int64_t>(chunks, kGiantChunkBlocks))),
                            dim3(kGiantThreads), glds, c->stream, segstart.p, n_next, pre.p, static_cast<int>(W),
                            raw.p, gbm.p);

@@ -69,6 +69,11 @@ struct Ctx {
     // into pageable memory would block the host on its own)
     int64_t* pinned = nullptr; // kPinnedSlots slots
     int64_t* pinned_dev = nullptr; // the same slots as kernels address them (they write scan totals there)
+    // coarse-build launch facts queried once: compute units, the LDS limits
+    // of the segment kernels, and the dedup kernel's workgroups per CU by LDS size
+    int cus = 0;
+    bool seg_lds_set = false;
+    std::map<size_t, int> dedup_per_cu;
     static constexpr int kPinnedSlots = 64;
     // batched-training autotune cache: key -> (mode, blocks per CU, chunk iterations)
     std::map<std::string, std::array<int, 3>> tune;
