@@ -37,7 +37,12 @@ namespace {
 
 using namespace train_detail;
 
-template <bool BF16, int D, int KMAX, class Off, int MODE>
+// LOOP (per-epoch mode, one epoch per launch): each wave takes its slots in
+// a grid-stride loop over a capped grid instead of one slot group per wave.
+// Measured faster on levels below kLoopMaxVertices and slower on level 0 of
+// the scale-20 graph, even at one iteration per wave, so it is a separate
+// kernel.
+template <bool BF16, int D, int KMAX, class Off, int MODE, bool LOOP = false>
 __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
     constexpr int L = Lanes<BF16, D>::kL;
     constexpr int G = Lanes<BF16, D>::kG;
@@ -72,8 +77,17 @@ __global__ __launch_bounds__(kBlock) void k_train(TrainParams P) {
             }
         }
         const int64_t limit = (MODE == kExplicit) ? P.nsrc : P.n;
-        const float l = visit<BF16, D, KMAX, Off, MODE>(P, slot, slot < limit, gl);
-        if (P.loss) wave_add_loss<L>(P.loss, l, gl);
+        if constexpr (LOOP) {
+            const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
+            for (int64_t w = wave; w * G < limit; w += waves) {   // wave-uniform bound
+                const int64_t s = w * G + grp;
+                const float l = visit<BF16, D, KMAX, Off, MODE>(P, s, s < limit, gl);
+                if (P.loss) wave_add_loss<L>(P.loss, l, gl);
+            }
+        } else {
+            const float l = visit<BF16, D, KMAX, Off, MODE>(P, slot, slot < limit, gl);
+            if (P.loss) wave_add_loss<L>(P.loss, l, gl);
+        }
     }
 }
 
@@ -202,6 +216,9 @@ __global__ __launch_bounds__(256) void k_add_updates(const Off* off, int64_t n, 
 // ---------------------------------------------------------------- dispatch
 using Launcher = void (*)(const TrainParams&, int64_t, hipStream_t);
 
+constexpr int64_t kLoopMaxVertices = 262144;   // levels below it run the LOOP kernel
+constexpr int64_t kLoopBlocks = 2560;           // its grid cap: two rounds of resident workgroups on 256 CUs
+
 template <bool BF16, int D, int KMAX, class Off, int MODE>
 void launch(const TrainParams& P, int64_t items, hipStream_t st) {
     constexpr int G = Lanes<BF16, D>::kG;
@@ -210,6 +227,13 @@ void launch(const TrainParams& P, int64_t items, hipStream_t st) {
     } else {
         const int64_t per_block = (kBlock / 64) * G;
         const int64_t blocks = ceil_div(items, per_block);
+        if constexpr (MODE == kEpoch) {
+            if (items == P.n && P.n < kLoopMaxVertices) {   // one epoch per launch
+                hipLaunchKernelGGL((k_train<BF16, D, KMAX, Off, MODE, true>),
+                                   dim3(static_cast<unsigned>(std::min(blocks, kLoopBlocks))), dim3(kBlock), 0, st, P);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_train<BF16, D, KMAX, Off, MODE>), dim3(static_cast<unsigned>(blocks)),
                            dim3(kBlock), 0, st, P);
     }
